@@ -1,0 +1,200 @@
+"""ctypes front end of the C oracle (see oracle.c for the passages each function follows).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the GPU library imports this module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+L2, IP = 0, 1
+SYNC_BSP, SYNC_STATIC, SYNC_ADAPTIVE = 0, 1, 2
+ALGO_BFIS, ALGO_TOPM, ALGO_SPEEDANN = 0, 1, 2
+
+
+class Stats(C.Structure):
+    _fields_ = [("global_steps", C.c_int64), ("substeps", C.c_int64), ("expansions", C.c_int64),
+                ("dist_comps", C.c_int64), ("merges", C.c_int64)]
+
+
+STATS_DTYPE = np.dtype([("global_steps", "<i8"), ("substeps", "<i8"), ("expansions", "<i8"),
+                        ("dist_comps", "<i8"), ("merges", "<i8")])
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (-O2, OpenMP over independent queries)."""
+    with _lock:
+        if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+            return _LIB_PATH
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
+               "-Wno-unused-parameter", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+        return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(_LIB_PATH)
+        f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        st = np.ctypeslib.ndpointer(STATS_DTYPE, flags="C_CONTIGUOUS")
+        i64, i32, dbl = C.c_int64, C.c_int32, C.c_double
+        L.or_distance.argtypes = [f32p, f32p, C.c_int, C.c_int]
+        L.or_distance.restype = C.c_float
+        L.or_knn.argtypes = [f32p, i64, C.c_int, i64, f32p, i64, i64, C.c_int, C.c_int, C.c_int, i32p, f32p]
+        L.or_knn.restype = None
+        L.or_search_batch.argtypes = [C.c_int, f32p, i64, C.c_int, i64, C.c_int, i32p, C.c_int, i32, f32p, i64,
+                                      i64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dbl, C.c_int, C.c_int,
+                                      i32p, f32p, st]
+        L.or_search_batch.restype = C.c_int
+        L.or_medoid.argtypes = [f32p, i64, C.c_int, i64]
+        L.or_medoid.restype = i64
+        L.or_prune.argtypes = [f32p, i64, C.c_int, i64, C.c_int, i32p, C.c_int, C.c_int, C.c_int, i32p]
+        L.or_prune.restype = None
+        L.or_repair.argtypes = [f32p, i64, C.c_int, i64, C.c_int, i32p, C.c_int, i32, C.c_int,
+                                C.POINTER(C.c_int64)]
+        L.or_repair.restype = i64
+        L.or_reachable.argtypes = [i32p, C.c_int, i64, i32, u8p]
+        L.or_reachable.restype = i64
+        _lib = L
+    return _lib
+
+
+def _metric(m) -> int:
+    if isinstance(m, str):
+        return {"l2": L2, "ip": IP}[m]
+    return int(m)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def distance(a, b, metric="l2") -> float:
+    a, b = _f32(a).ravel(), _f32(b).ravel()
+    return float(lib().or_distance(a, b, a.shape[0], _metric(metric)))
+
+
+def knn(base, queries, k, metric="l2", exclude_self=False):
+    """Exact top-k by key (distance, id) over all base vectors (linear scan)."""
+    base, queries = _f32(base), _f32(queries)
+    n, d = base.shape
+    nq = queries.shape[0]
+    ids = np.empty((nq, k), np.int32)
+    dists = np.empty((nq, k), np.float32)
+    lib().or_knn(base, n, d, d, queries, nq, d, k, _metric(metric), int(exclude_self), ids, dists)
+    return ids, dists
+
+
+def search(algo, base, adj, entry, queries, k, L, M=1, metric="l2", sync="adaptive", static_I=0,
+           rho=0.8, staged=True, max_substeps=0):
+    """Run one of the search algorithms for every query.  algo: "bfis" (Algorithm 1),
+    "topm" (Top-M, M fixed or staged) or "speedann" (Algorithm 3, lockstep)."""
+    base, queries = _f32(base), _f32(queries)
+    adj = np.ascontiguousarray(adj, dtype=np.int32)
+    n, d = base.shape
+    R = adj.shape[1]
+    nq = queries.shape[0]
+    a = {"bfis": ALGO_BFIS, "topm": ALGO_TOPM, "speedann": ALGO_SPEEDANN}[algo]
+    s = {"bsp": SYNC_BSP, "static": SYNC_STATIC, "adaptive": SYNC_ADAPTIVE}[sync] if isinstance(sync, str) else int(sync)
+    ids = np.empty((nq, k), np.int32)
+    dists = np.empty((nq, k), np.float32)
+    stats = np.zeros(nq, STATS_DTYPE)
+    rc = lib().or_search_batch(a, base, n, d, d, _metric(metric), adj, R, int(entry), queries, nq, d, int(k),
+                               int(L), int(M), s, int(static_I), float(rho), int(bool(staged)),
+                               int(max_substeps), ids, dists, stats)
+    if rc & 2:
+        raise MemoryError("oracle search: allocation failed")
+    return ids, dists, stats
+
+
+def bfis(base, adj, entry, queries, k, L, metric="l2"):
+    return search("bfis", base, adj, entry, queries, k, L, 1, metric)
+
+
+def topm(base, adj, entry, queries, k, L, M, staged=False, metric="l2"):
+    return search("topm", base, adj, entry, queries, k, L, M, metric, staged=staged)
+
+
+def speedann(base, adj, entry, queries, k, L, T, sync="adaptive", static_I=0, rho=0.8, staged=True,
+             metric="l2", max_substeps=0):
+    return search("speedann", base, adj, entry, queries, k, L, T, metric, sync, static_I, rho, staged,
+                  max_substeps)
+
+
+def medoid(base) -> int:
+    base = _f32(base)
+    n, d = base.shape
+    return int(lib().or_medoid(base, n, d, d))
+
+
+def prune(base, cand, R, mode="rng", metric="l2"):
+    base = _f32(base)
+    cand = np.ascontiguousarray(cand, dtype=np.int32)
+    n, d = base.shape
+    adj = np.empty((n, R), np.int32)
+    lib().or_prune(base, n, d, d, _metric(metric), cand, cand.shape[1], int(R), {"knn": 0, "rng": 1}[mode], adj)
+    return adj
+
+
+def repair(base, adj, entry, keep_local=1, metric="l2"):
+    """Connectivity repair in place; returns (bridges added, component count)."""
+    base = _f32(base)
+    assert adj.dtype == np.int32 and adj.flags.c_contiguous
+    n, d = base.shape
+    nc = C.c_int64(0)
+    added = lib().or_repair(base, n, d, d, _metric(metric), adj, adj.shape[1], int(entry), int(keep_local),
+                            C.byref(nc))
+    if added < 0:
+        raise RuntimeError("repair: no reachable vertex has a free slot")
+    return int(added), int(nc.value)
+
+
+def reachable(adj, entry):
+    adj = np.ascontiguousarray(adj, dtype=np.int32)
+    n = adj.shape[0]
+    mark = np.zeros(n, np.uint8)
+    cnt = lib().or_reachable(adj, adj.shape[1], n, int(entry), mark)
+    return int(cnt), mark.astype(bool)
+
+
+def build_graph(base, knn_k, R, prune_mode="rng", do_repair=True, keep_local=1, metric="l2"):
+    """Exact knn_k-NN candidates, row pruning to R, medoid entry, optional repair.
+    Returns (adj, entry, info)."""
+    base = _f32(base)
+    entry = medoid(base)
+    cand, _ = knn(base, base, knn_k, metric, exclude_self=True)
+    adj = prune(base, cand, R, prune_mode, metric)
+    info = {"bridges": 0, "components": None}
+    if do_repair:
+        info["bridges"], info["components"] = repair(base, adj, entry, keep_local, metric)
+    return adj, entry, info
+
+
+def recall(found_ids, true_ids, k=None) -> np.ndarray:
+    """Per-query Recall = |R' & R| / K (Sec. 2.1); padding ids (-1) never count."""
+    found_ids = np.asarray(found_ids)
+    true_ids = np.asarray(true_ids)
+    if k is None:
+        k = true_ids.shape[1]
+    out = np.empty(found_ids.shape[0])
+    for i in range(found_ids.shape[0]):
+        t = set(int(x) for x in true_ids[i, :k] if x >= 0)
+        f = set(int(x) for x in found_ids[i, :k] if x >= 0)
+        out[i] = len(t & f) / float(k)
+    return out
