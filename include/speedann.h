@@ -1,0 +1,172 @@
+/*
+ * speedann.h — C ABI of the MI355X (gfx950) implementation of the intra-query parallel
+ * graph search of Speed-ANN (Peng, Zhang, Li et al., arXiv 2201.13007).
+ *
+ * Conventions for every entry point
+ *   - Pointers named *_dev are device (HBM) pointers; all others are host pointers.
+ *   - The caller owns every buffer.  Nothing here frees a caller buffer.  An index
+ *     object borrows its device arrays: they must outlive it.
+ *   - Calls that take a hip_stream enqueue work on that stream (NULL = the default
+ *     stream) and return before it finishes, unless stated otherwise.
+ *   - Return value: SA_OK (0) or a negative sa_status.  sa_last_error() returns a
+ *     message for the calling thread's most recent failure.
+ *   - Squared l2 distance is reported for SA_L2: it ranks like the l2 distance the
+ *     paper uses (Sec. 2.1).  SA_IP reports the negated inner product, so that smaller
+ *     is closer for both metrics.
+ *   - Lists, results and ground truth are ordered by the key (distance, id) ascending:
+ *     equal distances go to the smaller id.
+ *   - Each distance is accumulated in double precision from the float32 inputs and
+ *     rounded once to float32 (round to nearest even).
+ */
+#ifndef SPEEDANN_H
+#define SPEEDANN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SA_OK = 0,
+    SA_EINVAL = -1,        /* invalid argument */
+    SA_ENOMEM = -2,        /* a device allocation failed (graph construction only) */
+    SA_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    SA_EUNSUPPORTED = -4,  /* valid but not supported (e.g. no gfx950 device) */
+    SA_ECAPACITY = -5      /* workspace too small, or a fixed capacity was exceeded */
+} sa_status;
+
+typedef enum { SA_L2 = 0, SA_IP = 1 } sa_metric;
+
+/* Synchronisation schedule of the local searches (Algorithm 3, CheckMetrics):
+ *   SA_SYNC_BSP       merge the local queues after every local step (the Top-M scheme
+ *                     of Sec. 4.1, bulk synchronous)
+ *   SA_SYNC_STATIC    merge after static_I local steps; static_I <= 0 never merges
+ *                     before the local queues run out of unchecked candidates
+ *                     (the no-synchronisation variant of Sec. 4.3)
+ *   SA_SYNC_ADAPTIVE  merge when the mean update position of the active workers is at
+ *                     least L * rho (Sec. 4.3, Algorithm 2) */
+typedef enum { SA_SYNC_BSP = 0, SA_SYNC_STATIC = 1, SA_SYNC_ADAPTIVE = 2 } sa_sync;
+
+typedef struct {
+    int32_t sync;           /* sa_sync; default SA_SYNC_ADAPTIVE */
+    int32_t static_I;       /* SA_SYNC_STATIC interval; default 0 */
+    double rho;             /* SA_SYNC_ADAPTIVE position ratio; default 0.8 (Sec. 5 uses 0.8/0.9).
+                               The test is mean(U) >= L * rho, evaluated in double precision. */
+    int32_t staged;         /* 1: expansion width starts at 1 and doubles after every merge
+                               (Sec. 4.2, Algorithm 3); 0: width M from the start. default 1 */
+    int32_t max_substeps;   /* stop a query after this many local steps (flag in stats);
+                               0 = 1<<22 */
+    int32_t lds_hash_slots; /* visited-set slots kept in on-chip LDS per query, power of
+                               two >= 64; 0 = chosen from L and M.  A query whose visited set
+                               outgrows half of it moves the set to the workspace. */
+    int32_t ws_hash_slots;  /* visited-set slots per query in the workspace, power of two;
+                               0 = chosen from L and M */
+} sa_search_params;
+
+/* Per-query counters written by sa_search when stats_dev is not NULL. */
+typedef struct {
+    int32_t global_steps;   /* global steps that dispatched work */
+    int32_t substeps;       /* lockstep local steps */
+    int32_t expansions;     /* candidates marked checked */
+    int32_t dist_comps;     /* distances computed (= visited vertices, entry included) */
+    int32_t merges;         /* merges of the local queues into the global queue */
+    int32_t flags;          /* SA_QFLAG_* */
+    uint64_t t_start;       /* device real-time counter (100 MHz) at query start / end */
+    uint64_t t_end;
+} sa_query_stats;
+
+#define SA_QFLAG_MAX_STEPS 1   /* stopped by max_substeps: result is the global queue then */
+#define SA_QFLAG_CAPACITY 2    /* the workspace visited set filled up: result is partial */
+#define SA_QFLAG_SPILLED 4     /* the visited set moved from LDS to the workspace */
+
+typedef struct sa_index sa_index;
+
+const char *sa_last_error(void);
+
+/* Fills *out with the defaults listed in sa_search_params. */
+void sa_default_params(sa_search_params *out);
+
+/* ------------------------------------------------------------------ exact search */
+
+/* Exact k nearest neighbours by linear scan (Sec. 2.1, the naive solution of Def. 1):
+ * for every query row, the k smallest keys (distance, id) over all n base rows.
+ *   base_dev     n rows of d float32, row stride ld floats (ld >= d), 16-byte aligned
+ *   queries_dev  nq rows, stride ldq
+ *   exclude_self when queries_dev == base_dev: row i skips base id i (graph construction)
+ *   ids_dev      nq x k int32, dists_dev nq x k float32 (row-major); padded with
+ *                (-1, +inf) when n (minus the excluded row) < k
+ * 1 <= k <= 256.  Enqueued on hip_stream. */
+int sa_knn(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float *queries_dev, int64_t nq,
+           int64_t ldq, int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids_dev, float *dists_dev,
+           void *hip_stream);
+
+/* ------------------------------------------------------------------ graph construction
+ * The paper searches a graph built offline (NSG, Sec. 2.2) and does not construct one.
+ * These calls build the fixed-width graph the search reads: adj_dev is n x R int32,
+ * row-major, each row's out-neighbours first, padded with -1. */
+
+/* Entry point: the row nearest to the mean of all rows (double precision), ties to the
+ * smaller id.  Synchronous; result in *entry_out. */
+int sa_medoid(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t *entry_out, void *hip_stream);
+
+/* Row pruning of candidate lists cand_dev (n x kc int32, each row sorted by key, as
+ * sa_knn returns them with exclude_self).  prune 0: keep the first R.  prune 1
+ * (relative-neighbourhood rule): scan the candidates in order, keep c unless an already
+ * kept s has d(s, c) < d(p, c), stop at R kept.  Enqueued on hip_stream. */
+int sa_prune(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, const int32_t *cand_dev,
+             int32_t kc, int32_t R, int32_t prune, int32_t *adj_dev, void *hip_stream);
+
+/* Connectivity repair of adj_dev in place (synchronous; copies the graph to the host):
+ * (1) weakly connected components, each with its medoid as representative; (2) every
+ * representative and the entry get a new row: their first keep_local edges, then up to
+ * R - keep_local links to other representatives chosen by the relative-neighbourhood
+ * rule and filled with the nearest ones; (3) in increasing id order every vertex not
+ * reachable from the entry gets an edge from the nearest reachable vertex with a free
+ * slot.  Writes the number of (3) edges and components to the outputs when not NULL.
+ * SA_ECAPACITY if (3) finds no reachable vertex with a free slot. */
+int sa_repair(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, int32_t *adj_dev,
+              int32_t R, int32_t entry, int32_t keep_local, int64_t *bridges_out, int64_t *components_out,
+              void *hip_stream);
+
+/* Whole pipeline: entry = sa_medoid; candidates = sa_knn(knn_k, exclude_self);
+ * adj = sa_prune; if repair, sa_repair(keep_local).  Synchronous.  Allocates its
+ * temporaries with hipMalloc and frees them before returning. */
+int sa_build_graph(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, int32_t knn_k,
+                   int32_t R, int32_t prune, int32_t repair, int32_t keep_local, int32_t *adj_dev,
+                   int32_t *entry_out, int64_t *bridges_out, int64_t *components_out, void *hip_stream);
+
+/* ------------------------------------------------------------------ the search */
+
+/* Wraps borrowed device arrays: vec_dev (n rows of d float32, stride ld floats,
+ * 16-byte aligned, ld % 4 == 0, ld >= d), adj_dev (n x R int32, -1 padded, ids in
+ * [0, n), no id twice in a row), entry in [0, n).  1 <= R <= 64, n < 2^31. */
+int sa_index_create(const float *vec_dev, int64_t n, int32_t d, int64_t ld, int32_t metric,
+                    const int32_t *adj_dev, int32_t R, int32_t entry, sa_index **out);
+void sa_index_destroy(sa_index *index);
+
+/* Bytes of workspace sa_search needs for nq queries (visited sets that outgrow LDS). */
+size_t sa_search_workspace_bytes(const sa_index *index, int64_t nq, int32_t k, int32_t L, int32_t M,
+                                 const sa_search_params *params);
+
+/* Intra-query parallel search (Algorithm 3; Algorithm 1 when M = 1), one workgroup per
+ * query and one wavefront per worker:
+ *   queries_dev  nq x d float32, stride ldq floats (16-byte aligned rows)
+ *   k, L         results per query and queue capacity, 1 <= k <= L <= 1024
+ *   M            workers (the paper's T, the maximum expansion width), 1 <= M <= 16
+ *   params       NULL for defaults
+ *   ids_dev      nq x k int32, dists_dev nq x k float32; padded with (-1, +inf) when
+ *                fewer than k vertices were reached
+ *   stats_dev    NULL or nq sa_query_stats
+ *   workspace    sa_search_workspace_bytes(...) bytes of device memory, 256-byte aligned
+ * Allocates nothing.  Enqueued on hip_stream. */
+int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64_t ldq, int32_t k, int32_t L,
+              int32_t M, const sa_search_params *params, int32_t *ids_dev, float *dists_dev,
+              sa_query_stats *stats_dev, void *workspace, size_t ws_bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPEEDANN_H */

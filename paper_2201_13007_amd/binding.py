@@ -1,0 +1,240 @@
+"""Python binding of libspeedann (include/speedann.h): argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm); every step of the search, the
+exact kNN and the graph construction runs in the library.  There is no CPU fallback:
+if the built library or a gfx950 device is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspeedann.so")
+
+SA_L2, SA_IP = 0, 1
+SYNC = {"bsp": 0, "static": 1, "adaptive": 2}
+QFLAG_MAX_STEPS, QFLAG_CAPACITY, QFLAG_SPILLED = 1, 2, 4
+
+EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_medoid", "sa_prune", "sa_repair",
+           "sa_build_graph", "sa_index_create", "sa_index_destroy", "sa_search_workspace_bytes", "sa_search"]
+
+
+class SearchParams(C.Structure):
+    _fields_ = [("sync", C.c_int32), ("static_I", C.c_int32), ("rho", C.c_double), ("staged", C.c_int32),
+                ("max_substeps", C.c_int32), ("lds_hash_slots", C.c_int32), ("ws_hash_slots", C.c_int32)]
+
+
+# sa_query_stats as a numpy/torch view: 6 int32 + 2 uint64 = 40 bytes
+STATS_FIELDS = ["global_steps", "substeps", "expansions", "dist_comps", "merges", "flags"]
+STATS_BYTES = 40
+
+
+class SpeedAnnError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SpeedAnnError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
+        L.sa_last_error.restype = C.c_char_p
+        L.sa_default_params.argtypes = [C.POINTER(SearchParams)]
+        L.sa_knn.argtypes = [vp, i64, i32, i64, vp, i64, i64, i32, i32, i32, vp, vp, vp]
+        L.sa_medoid.argtypes = [vp, i64, i32, i64, C.POINTER(C.c_int32), vp]
+        L.sa_prune.argtypes = [vp, i64, i32, i64, i32, vp, i32, i32, i32, vp, vp]
+        L.sa_repair.argtypes = [vp, i64, i32, i64, i32, vp, i32, i32, i32, C.POINTER(C.c_int64),
+                                C.POINTER(C.c_int64), vp]
+        L.sa_build_graph.argtypes = [vp, i64, i32, i64, i32, i32, i32, i32, i32, i32, vp, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
+        L.sa_index_create.argtypes = [vp, i64, i32, i64, i32, vp, i32, i32, C.POINTER(vp)]
+        L.sa_index_destroy.argtypes = [vp]
+        L.sa_index_destroy.restype = None
+        L.sa_search_workspace_bytes.argtypes = [vp, i64, i32, i32, i32, C.POINTER(SearchParams)]
+        L.sa_search_workspace_bytes.restype = sz
+        L.sa_search.argtypes = [vp, vp, i64, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp, sz, vp]
+        for name in ("sa_knn", "sa_medoid", "sa_prune", "sa_repair", "sa_build_graph", "sa_index_create",
+                     "sa_search"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise SpeedAnnError(f"{what} failed ({rc}): {lib().sa_last_error().decode()}")
+
+
+def _metric(m) -> int:
+    return {"l2": SA_L2, "ip": SA_IP}[m] if isinstance(m, str) else int(m)
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _mat(x: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise SpeedAnnError(f"{name} must be a device tensor")
+    if x.dtype != torch.float32 or x.dim() != 2:
+        raise SpeedAnnError(f"{name} must be a 2-d float32 tensor")
+    if x.stride(1) != 1:
+        x = x.contiguous()
+    return x
+
+
+def pad_dim(x: torch.Tensor) -> torch.Tensor:
+    """Pads rows with zero columns to a multiple of 4 (zero columns change no distance)."""
+    d = x.shape[1]
+    if d % 4 == 0 and x.stride(0) % 4 == 0 and x.data_ptr() % 16 == 0:
+        return x
+    d4 = (d + 3) // 4 * 4
+    out = torch.zeros((x.shape[0], d4), dtype=x.dtype, device=x.device)
+    out[:, :d] = x
+    return out
+
+
+def knn(base: torch.Tensor, queries: torch.Tensor, k: int, metric="l2", exclude_self=False, stream=None):
+    """Exact top-k by (distance, id) over all rows of base (linear scan on the GPU)."""
+    base = pad_dim(_mat(base, "base"))
+    queries = base if (exclude_self and queries is None) else pad_dim(_mat(queries, "queries"))
+    nq = queries.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=base.device)
+    dists = torch.empty((nq, k), dtype=torch.float32, device=base.device)
+    _check(lib().sa_knn(base.data_ptr(), base.shape[0], base.shape[1], base.stride(0), queries.data_ptr(), nq,
+                        queries.stride(0), k, _metric(metric), int(exclude_self), ids.data_ptr(), dists.data_ptr(),
+                        _stream(stream)), "sa_knn")
+    return ids, dists
+
+
+def medoid(base: torch.Tensor, stream=None) -> int:
+    base = pad_dim(_mat(base, "base"))
+    out = C.c_int32(0)
+    _check(lib().sa_medoid(base.data_ptr(), base.shape[0], base.shape[1], base.stride(0), C.byref(out),
+                           _stream(stream)), "sa_medoid")
+    return int(out.value)
+
+
+def prune(base: torch.Tensor, cand: torch.Tensor, R: int, mode="rng", metric="l2", stream=None) -> torch.Tensor:
+    base = pad_dim(_mat(base, "base"))
+    cand = cand.to(torch.int32).contiguous()
+    adj = torch.empty((base.shape[0], R), dtype=torch.int32, device=base.device)
+    _check(lib().sa_prune(base.data_ptr(), base.shape[0], base.shape[1], base.stride(0), _metric(metric),
+                          cand.data_ptr(), cand.shape[1], R, {"knn": 0, "rng": 1}[mode], adj.data_ptr(),
+                          _stream(stream)), "sa_prune")
+    return adj
+
+
+def repair(base: torch.Tensor, adj: torch.Tensor, entry: int, keep_local=1, metric="l2", stream=None):
+    """Connectivity repair of adj in place; returns (bridges, components)."""
+    base = pad_dim(_mat(base, "base"))
+    assert adj.dtype == torch.int32 and adj.is_contiguous()
+    b, c = C.c_int64(0), C.c_int64(0)
+    _check(lib().sa_repair(base.data_ptr(), base.shape[0], base.shape[1], base.stride(0), _metric(metric),
+                           adj.data_ptr(), adj.shape[1], int(entry), int(keep_local), C.byref(b), C.byref(c),
+                           _stream(stream)), "sa_repair")
+    return int(b.value), int(c.value)
+
+
+def build_graph(base: torch.Tensor, knn_k: int, R: int, prune_mode="rng", do_repair=True, keep_local=1,
+                metric="l2", stream=None):
+    """Returns (adj, entry, info) built on the GPU."""
+    base = pad_dim(_mat(base, "base"))
+    n = base.shape[0]
+    adj = torch.empty((n, R), dtype=torch.int32, device=base.device)
+    entry, b, c = C.c_int32(0), C.c_int64(0), C.c_int64(0)
+    _check(lib().sa_build_graph(base.data_ptr(), n, base.shape[1], base.stride(0), _metric(metric), knn_k, R,
+                                {"knn": 0, "rng": 1}[prune_mode], int(bool(do_repair)), int(keep_local),
+                                adj.data_ptr(), C.byref(entry), C.byref(b), C.byref(c), _stream(stream)),
+           "sa_build_graph")
+    return adj, int(entry.value), {"bridges": int(b.value), "components": int(c.value)}
+
+
+def make_params(sync="adaptive", static_I=0, rho=0.8, staged=True, max_substeps=0, lds_hash_slots=0,
+                ws_hash_slots=0) -> SearchParams:
+    p = SearchParams()
+    lib().sa_default_params(C.byref(p))
+    p.sync = SYNC[sync] if isinstance(sync, str) else int(sync)
+    p.static_I = int(static_I)
+    p.rho = float(rho)
+    p.staged = int(bool(staged))
+    p.max_substeps = int(max_substeps)
+    p.lds_hash_slots = int(lds_hash_slots)
+    p.ws_hash_slots = int(ws_hash_slots)
+    return p
+
+
+@dataclass
+class SearchResult:
+    ids: torch.Tensor
+    dists: torch.Tensor
+    stats: torch.Tensor | None   # (nq, 10) int32 view of sa_query_stats, or None
+
+    def stat(self, name: str) -> torch.Tensor:
+        return self.stats[:, STATS_FIELDS.index(name)]
+
+    def times(self) -> torch.Tensor:
+        """(t_start, t_end) device real-time counter values per query (100 MHz)."""
+        return self.stats.view(torch.int64)[:, 3:5]
+
+
+class Index:
+    """A graph index over device arrays (borrowed: keep vec and adj alive)."""
+
+    def __init__(self, vec: torch.Tensor, adj: torch.Tensor, entry: int, metric="l2"):
+        vec = pad_dim(_mat(vec, "vectors"))
+        if adj.dtype != torch.int32 or not adj.is_cuda or not adj.is_contiguous():
+            raise SpeedAnnError("adj must be a contiguous int32 device tensor")
+        self.vec, self.adj, self.entry, self.metric = vec, adj, int(entry), metric
+        h = C.c_void_p(0)
+        _check(lib().sa_index_create(vec.data_ptr(), vec.shape[0], vec.shape[1], vec.stride(0), _metric(metric),
+                                     adj.data_ptr(), adj.shape[1], self.entry, C.byref(h)), "sa_index_create")
+        self._h = h
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().sa_index_destroy(h)
+            self._h = None
+
+    def workspace_bytes(self, nq, k, L, M, params: SearchParams) -> int:
+        return int(lib().sa_search_workspace_bytes(self._h, nq, k, L, M, C.byref(params)))
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.vec.device)
+        return self._ws
+
+    def search(self, queries: torch.Tensor, k: int, L: int, M: int = 1, params: SearchParams | None = None,
+               stats=False, stream=None, out=None, **kw) -> SearchResult:
+        if params is None:
+            params = make_params(**kw)
+        queries = pad_dim(_mat(queries, "queries"))
+        if queries.shape[1] != self.vec.shape[1]:
+            raise SpeedAnnError("query dimension does not match the index")
+        nq = queries.shape[0]
+        dev = self.vec.device
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+            dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+            st = torch.empty((nq, STATS_BYTES // 4), dtype=torch.int32, device=dev) if stats else None
+        else:
+            ids, dists, st = out
+        nbytes = self.workspace_bytes(nq, k, L, M, params)
+        ws = self.workspace(nbytes)
+        _check(lib().sa_search(self._h, queries.data_ptr(), nq, queries.stride(0), k, L, M, C.byref(params),
+                               ids.data_ptr(), dists.data_ptr(), st.data_ptr() if st is not None else None,
+                               ws.data_ptr(), ws.numel(), _stream(stream)), "sa_search")
+        return SearchResult(ids, dists, st)

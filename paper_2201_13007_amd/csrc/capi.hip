@@ -1,0 +1,244 @@
+// C ABI of libspeedann: argument validation, error strings, and the calls that string
+// the kernels together.  Declarations and their contracts are in include/speedann.h.
+#include "sa_internal.h"
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+namespace sa {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return set_error(SA_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int medoid_device(const float *base, int64_t n, int d, int64_t ld, int32_t *out, hipStream_t s);
+int prune_device(const float *base, int64_t n, int d, int64_t ld, int metric, const int32_t *cand, int kc, int R,
+                 int mode, int32_t *adj, hipStream_t s);
+int repair_device(const float *base, int64_t n, int d, int64_t ld, int metric, int32_t *adj_dev, int R,
+                  int32_t entry, int keep_local, int64_t *bridges_out, int64_t *ncomp_out, hipStream_t s);
+
+static int check_device()
+{
+    static int cached = 0;   // 0 unknown, 1 ok, negative error
+    if (cached == 1) return SA_OK;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(SA_EUNSUPPORTED, "device %d is %s; this library is built for gfx950 only", dev,
+                         prop.gcnArchName);
+    cached = 1;
+    return SA_OK;
+}
+
+static int check_matrix(const void *p, int64_t rows, int32_t d, int64_t ld, const char *name)
+{
+    if (rows < 0) return set_error(SA_EINVAL, "%s: negative row count", name);
+    if (rows > 0 && p == nullptr) return set_error(SA_EINVAL, "%s is NULL", name);
+    if (d < 4 || d % 4 != 0 || d > 4096)
+        return set_error(SA_EINVAL, "%s: d=%d must be a multiple of 4 in [4, 4096] (pad with zeros)", name, d);
+    if (ld < d || ld % 4 != 0) return set_error(SA_EINVAL, "%s: row stride %lld must be >= d and a multiple of 4", name, (long long)ld);
+    if (((uintptr_t)p & 15u) != 0) return set_error(SA_EINVAL, "%s must be 16-byte aligned", name);
+    return SA_OK;
+}
+
+}  // namespace sa
+
+using namespace sa;
+
+struct sa_index {
+    const float *vec;
+    int64_t n, ld;
+    int32_t d, metric;
+    const int32_t *adj;
+    int32_t R, entry;
+};
+
+extern "C" {
+
+const char *sa_last_error(void) { return g_last_error.c_str(); }
+
+void sa_default_params(sa_search_params *out)
+{
+    if (!out) return;
+    std::memset(out, 0, sizeof(*out));
+    out->sync = SA_SYNC_ADAPTIVE;
+    out->static_I = 0;
+    out->rho = 0.8;
+    out->staged = 1;
+}
+
+int sa_knn(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float *queries_dev, int64_t nq, int64_t ldq,
+           int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids_dev, float *dists_dev, void *hip_stream)
+{
+    int rc;
+    if ((rc = check_matrix(base_dev, n, d, ld, "base")) != SA_OK) return rc;
+    if ((rc = check_matrix(queries_dev, nq, d, ldq, "queries")) != SA_OK) return rc;
+    if (n >= (int64_t(1) << 31)) return set_error(SA_EINVAL, "n must be < 2^31");
+    if (k < 1 || k > 256) return set_error(SA_EINVAL, "k=%d must be in [1, 256]", k);
+    if (metric != SA_L2 && metric != SA_IP) return set_error(SA_EINVAL, "unknown metric %d", metric);
+    if (nq > 0 && (ids_dev == nullptr || dists_dev == nullptr)) return set_error(SA_EINVAL, "output is NULL");
+    if (exclude_self && nq > n) return set_error(SA_EINVAL, "exclude_self needs the queries to be base rows");
+    if ((rc = check_device()) != SA_OK) return rc;
+    return launch_knn(base_dev, n, d, ld, queries_dev, nq, ldq, k, metric, exclude_self, ids_dev, dists_dev,
+                      (hipStream_t)hip_stream);
+}
+
+int sa_medoid(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t *entry_out, void *hip_stream)
+{
+    int rc;
+    if ((rc = check_matrix(base_dev, n, d, ld, "base")) != SA_OK) return rc;
+    if (n < 1) return set_error(SA_EINVAL, "n must be >= 1");
+    if (!entry_out) return set_error(SA_EINVAL, "entry_out is NULL");
+    if ((rc = check_device()) != SA_OK) return rc;
+    return medoid_device(base_dev, n, d, ld, entry_out, (hipStream_t)hip_stream);
+}
+
+int sa_prune(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, const int32_t *cand_dev,
+             int32_t kc, int32_t R, int32_t prune, int32_t *adj_dev, void *hip_stream)
+{
+    int rc;
+    if ((rc = check_matrix(base_dev, n, d, ld, "base")) != SA_OK) return rc;
+    if (kc < 1 || kc > 64) return set_error(SA_EINVAL, "candidate list width %d must be in [1, 64]", kc);
+    if (R < 1 || R > 64) return set_error(SA_EINVAL, "R=%d must be in [1, 64]", R);
+    if (prune != 0 && prune != 1) return set_error(SA_EINVAL, "prune must be 0 or 1");
+    if (metric != SA_L2 && metric != SA_IP) return set_error(SA_EINVAL, "unknown metric %d", metric);
+    if (n > 0 && (!cand_dev || !adj_dev)) return set_error(SA_EINVAL, "NULL candidate or adjacency array");
+    if ((rc = check_device()) != SA_OK) return rc;
+    return prune_device(base_dev, n, d, ld, metric, cand_dev, kc, R, prune, adj_dev, (hipStream_t)hip_stream);
+}
+
+int sa_repair(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, int32_t *adj_dev, int32_t R,
+              int32_t entry, int32_t keep_local, int64_t *bridges_out, int64_t *components_out, void *hip_stream)
+{
+    int rc;
+    if ((rc = check_matrix(base_dev, n, d, ld, "base")) != SA_OK) return rc;
+    if (n < 1 || n >= (int64_t(1) << 31)) return set_error(SA_EINVAL, "n must be in [1, 2^31)");
+    if (R < 1 || R > 64) return set_error(SA_EINVAL, "R=%d must be in [1, 64]", R);
+    if (entry < 0 || entry >= n) return set_error(SA_EINVAL, "entry %d out of range", entry);
+    if (keep_local < 0 || keep_local > R) return set_error(SA_EINVAL, "keep_local must be in [0, R]");
+    if (!adj_dev) return set_error(SA_EINVAL, "adjacency is NULL");
+    if ((rc = check_device()) != SA_OK) return rc;
+    return repair_device(base_dev, n, d, ld, metric, adj_dev, R, entry, keep_local, bridges_out, components_out,
+                         (hipStream_t)hip_stream);
+}
+
+int sa_build_graph(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, int32_t knn_k, int32_t R,
+                   int32_t prune, int32_t repair, int32_t keep_local, int32_t *adj_dev, int32_t *entry_out,
+                   int64_t *bridges_out, int64_t *components_out, void *hip_stream)
+{
+    int rc;
+    if ((rc = check_matrix(base_dev, n, d, ld, "base")) != SA_OK) return rc;
+    if (n < 2 || n >= (int64_t(1) << 31)) return set_error(SA_EINVAL, "n must be in [2, 2^31)");
+    if (knn_k < 1 || knn_k > 64) return set_error(SA_EINVAL, "knn_k=%d must be in [1, 64]", knn_k);
+    if (R < 1 || R > 64) return set_error(SA_EINVAL, "R=%d must be in [1, 64]", R);
+    if (!adj_dev || !entry_out) return set_error(SA_EINVAL, "NULL output");
+    if ((rc = check_device()) != SA_OK) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if ((rc = medoid_device(base_dev, n, d, ld, entry_out, s)) != SA_OK) return rc;
+    int32_t *cand = nullptr;
+    float *cd = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&cand), sizeof(int32_t) * n * knn_k) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&cd), sizeof(float) * n * knn_k) != hipSuccess) {
+        if (cand) (void)hipFree(cand);
+        return set_error(SA_ENOMEM, "build_graph: candidate lists do not fit");
+    }
+    rc = launch_knn(base_dev, n, d, ld, base_dev, n, ld, knn_k, metric, 1, cand, cd, s);
+    if (rc == SA_OK) rc = prune_device(base_dev, n, d, ld, metric, cand, knn_k, R, prune, adj_dev, s);
+    if (rc == SA_OK) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = hip_fail(e, "build_graph");
+    }
+    (void)hipFree(cand);
+    (void)hipFree(cd);
+    if (bridges_out) *bridges_out = 0;
+    if (components_out) *components_out = 0;
+    if (rc == SA_OK && repair)
+        rc = repair_device(base_dev, n, d, ld, metric, adj_dev, R, *entry_out, keep_local, bridges_out, components_out, s);
+    return rc;
+}
+
+int sa_index_create(const float *vec_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, const int32_t *adj_dev,
+                    int32_t R, int32_t entry, sa_index **out)
+{
+    int rc;
+    if (!out) return set_error(SA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if ((rc = check_matrix(vec_dev, n, d, ld, "vectors")) != SA_OK) return rc;
+    if (n < 1 || n >= (int64_t(1) << 31)) return set_error(SA_EINVAL, "n must be in [1, 2^31)");
+    if (R < 1 || R > 64) return set_error(SA_EINVAL, "R=%d must be in [1, 64]", R);
+    if (entry < 0 || entry >= n) return set_error(SA_EINVAL, "entry %d out of range [0, %lld)", entry, (long long)n);
+    if (metric != SA_L2 && metric != SA_IP) return set_error(SA_EINVAL, "unknown metric %d", metric);
+    if (!adj_dev) return set_error(SA_EINVAL, "adjacency is NULL");
+    sa_index *ix = new (std::nothrow) sa_index;
+    if (!ix) return set_error(SA_ENOMEM, "out of host memory");
+    ix->vec = vec_dev; ix->n = n; ix->ld = ld; ix->d = d; ix->metric = metric;
+    ix->adj = adj_dev; ix->R = R; ix->entry = entry;
+    *out = ix;
+    return SA_OK;
+}
+
+void sa_index_destroy(sa_index *index) { delete index; }
+
+static int check_search(const sa_index *ix, int64_t nq, int32_t k, int32_t L, int32_t M, const sa_search_params &p)
+{
+    if (!ix) return set_error(SA_EINVAL, "index is NULL");
+    if (nq < 0 || nq > 0x7FFFFFFF) return set_error(SA_EINVAL, "nq=%lld out of range", (long long)nq);
+    if (k < 1 || L < k || L > 1024) return set_error(SA_EINVAL, "need 1 <= k <= L <= 1024 (k=%d, L=%d)", k, L);
+    if (M < 1 || M > 16) return set_error(SA_EINVAL, "M=%d must be in [1, 16]", M);
+    if (p.sync < SA_SYNC_BSP || p.sync > SA_SYNC_ADAPTIVE) return set_error(SA_EINVAL, "unknown sync %d", p.sync);
+    if (!(p.rho >= 0.0f) || !std::isfinite(p.rho)) return set_error(SA_EINVAL, "rho must be finite and >= 0");
+    if (p.max_substeps < 0) return set_error(SA_EINVAL, "max_substeps must be >= 0");
+    return SA_OK;
+}
+
+size_t sa_search_workspace_bytes(const sa_index *index, int64_t nq, int32_t k, int32_t L, int32_t M,
+                                 const sa_search_params *params)
+{
+    sa_search_params p;
+    if (params) p = *params;
+    else sa_default_params(&p);
+    if (check_search(index, nq, k, L, M, p) != SA_OK) return 0;
+    return search_workspace_bytes(nq, L, M, p, index->R);
+}
+
+int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64_t ldq, int32_t k, int32_t L,
+              int32_t M, const sa_search_params *params, int32_t *ids_dev, float *dists_dev,
+              sa_query_stats *stats_dev, void *workspace, size_t ws_bytes, void *hip_stream)
+{
+    sa_search_params p;
+    if (params) p = *params;
+    else sa_default_params(&p);
+    int rc;
+    if ((rc = check_search(index, nq, k, L, M, p)) != SA_OK) return rc;
+    if ((rc = check_matrix(queries_dev, nq, index->d, ldq, "queries")) != SA_OK) return rc;
+    if (nq > 0 && (!ids_dev || !dists_dev)) return set_error(SA_EINVAL, "output is NULL");
+    if ((rc = check_device()) != SA_OK) return rc;
+    SearchLaunch a;
+    a.vec = index->vec; a.ld = index->ld; a.n = index->n; a.d = index->d; a.metric = index->metric;
+    a.adj = index->adj; a.R = index->R; a.entry = index->entry;
+    a.queries = queries_dev; a.ldq = ldq; a.nq = nq; a.k = k; a.L = L; a.M = M; a.p = p;
+    a.ids = ids_dev; a.dists = dists_dev; a.stats = stats_dev; a.workspace = workspace; a.ws_bytes = ws_bytes;
+    return launch_search(a, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"

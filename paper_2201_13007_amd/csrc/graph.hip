@@ -1,0 +1,449 @@
+// Graph construction for the search (the paper takes a prebuilt NSG graph, Sec. 2.2;
+// this builds the fixed-width graph the kernels read): the medoid entry point, row
+// pruning of exact candidate lists, and a connectivity repair.
+//
+// Every distance here is computed by one thread walking the dimensions in index order in
+// double precision (separately rounded multiply and add) and rounded once to float, so
+// each pruning and bridging decision is reproducible bit for bit.
+#include "sa_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+namespace sa {
+namespace {
+
+__device__ float dist_seq(const float *a, const float *b, int d, int metric)
+{
+    double acc = 0.0;
+    if (metric == SA_L2) {
+        for (int i = 0; i < d; i += 4) {
+            const float4 x = *reinterpret_cast<const float4 *>(a + i);
+            const float4 y = *reinterpret_cast<const float4 *>(b + i);
+            double t;
+            t = (double)x.x - (double)y.x; acc += t * t;
+            t = (double)x.y - (double)y.y; acc += t * t;
+            t = (double)x.z - (double)y.z; acc += t * t;
+            t = (double)x.w - (double)y.w; acc += t * t;
+        }
+        return (float)acc;
+    }
+    for (int i = 0; i < d; i += 4) {
+        const float4 x = *reinterpret_cast<const float4 *>(a + i);
+        const float4 y = *reinterpret_cast<const float4 *>(b + i);
+        acc += (double)x.x * (double)y.x;
+        acc += (double)x.y * (double)y.y;
+        acc += (double)x.z * (double)y.z;
+        acc += (double)x.w * (double)y.w;
+    }
+    return (float)(-acc);
+}
+
+// ---------------------------------------------------------------- medoid
+
+constexpr int MED_CHUNK = 4096;
+
+__global__ void colsum_partial(const float *base, int64_t n, int d, int64_t ld, double *part)
+{
+    const int64_t r0 = (int64_t)blockIdx.x * MED_CHUNK;
+    const int64_t r1 = min(n, r0 + MED_CHUNK);
+    for (int c = threadIdx.x; c < d; c += blockDim.x) {
+        double s = 0.0;
+        for (int64_t r = r0; r < r1; ++r) s += (double)base[r * ld + c];
+        part[(int64_t)blockIdx.x * d + c] = s;
+    }
+}
+
+__global__ void colsum_final(const double *part, int64_t nchunks, int d, int64_t n, double *mean)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d; c += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t b = 0; b < nchunks; ++b) s += part[b * d + c];
+        mean[c] = s / (double)n;
+    }
+}
+
+__global__ void dist_to_mean(const float *base, int64_t n, int d, int64_t ld, const double *mean, double *bestd,
+                             int64_t *besti)
+{
+    __shared__ double sd[256];
+    __shared__ int64_t si[256];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = INFINITY;
+    int64_t id = INT64_MAX;
+    if (r < n) {
+        acc = 0.0;
+        for (int c = 0; c < d; ++c) {
+            double t = (double)base[r * ld + c] - mean[c];
+            acc += t * t;
+        }
+        id = r;
+    }
+    sd[threadIdx.x] = acc;
+    si[threadIdx.x] = id;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            double od = sd[threadIdx.x + s];
+            int64_t oi = si[threadIdx.x + s];
+            if (od < sd[threadIdx.x] || (od == sd[threadIdx.x] && oi < si[threadIdx.x])) {
+                sd[threadIdx.x] = od;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        bestd[blockIdx.x] = sd[0];
+        besti[blockIdx.x] = si[0];
+    }
+}
+
+// ---------------------------------------------------------------- pruning
+
+__global__ void prune_kernel(const float *base, int64_t n, int d, int64_t ld, int metric, const int32_t *cand,
+                             int kc, int R, int mode, int32_t *adj)
+{
+    __shared__ int32_t kept_all[4][64];
+    const int wv = threadIdx.x >> 6, lane = __lane_id();
+    const int64_t p = (int64_t)blockIdx.x * 4 + wv;
+    if (p >= n) return;
+    int32_t *kept = kept_all[wv];
+    int32_t c_mine = lane < kc ? cand[p * kc + lane] : -1;
+    if (c_mine >= n) c_mine = -1;   // malformed candidates are ignored like padding
+    int nk = 0;
+    if (mode == 0) {
+        const uint64_t m = __ballot(c_mine >= 0);
+        const int pos = __popcll(m & ((1ull << lane) - 1ull));
+        if (c_mine >= 0 && pos < R) kept[pos] = c_mine;
+        nk = min(R, __popcll(m));
+    } else {
+        const float dpc_mine = c_mine >= 0 ? dist_seq(base + p * ld, base + (int64_t)c_mine * ld, d, metric) : 0.f;
+        for (int j = 0; j < kc && nk < R; ++j) {
+            const int32_t c = __shfl(c_mine, j, 64);
+            if (c < 0) continue;
+            const float dpc = __shfl(dpc_mine, j, 64);
+            bool occl = false;
+            if (lane < nk) {
+                const int32_t s = kept[lane];
+                occl = dist_seq(base + (int64_t)s * ld, base + (int64_t)c * ld, d, metric) < dpc;
+            }
+            if (__ballot(occl) == 0) {
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) kept[nk] = c;
+                __builtin_amdgcn_wave_barrier();
+                ++nk;
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int j = lane; j < R; j += 64) adj[p * R + j] = j < nk ? kept[j] : -1;
+}
+
+// ---------------------------------------------------------------- repair helpers
+
+// key (distance to u, id) of the nearest vertex w with mask[w] and deg[w] < R
+__global__ void nearest_marked(const float *base, int64_t n, int d, int64_t ld, int metric, const uint8_t *mask,
+                               const int32_t *deg, int R, int32_t u, unsigned long long *result)
+{
+    __shared__ unsigned long long sk[256];
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long key = KEY_EMPTY;
+    if (w < n && mask[w] && deg[w] < R) {
+        float dd = dist_seq(base + w * ld, base + (int64_t)u * ld, d, metric);
+        key = make_key(dd, (int32_t)w);
+    }
+    sk[threadIdx.x] = key;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s && sk[threadIdx.x + s] < sk[threadIdx.x]) sk[threadIdx.x] = sk[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && sk[0] != KEY_EMPTY) atomicMin(result, sk[0]);
+}
+
+__global__ void set_marks(uint8_t *mask, const int32_t *list, int64_t cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) mask[list[i]] = 1;
+}
+
+__global__ void fill_u64(unsigned long long *p, unsigned long long v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// host-side distance with the same arithmetic as dist_seq
+float host_dist(const float *a, const float *b, int d, int metric)
+{
+    double acc = 0.0;
+    if (metric == SA_L2) {
+        for (int i = 0; i < d; ++i) {
+            double t = (double)a[i] - (double)b[i];
+            acc += t * t;
+        }
+        return (float)acc;
+    }
+    for (int i = 0; i < d; ++i) acc += (double)a[i] * (double)b[i];
+    return (float)(-acc);
+}
+
+bool key_less_host(float da, int32_t ia, float db, int32_t ib) { return da < db || (da == db && ia < ib); }
+
+// medoid of a set of rows: mean summed in the listed order, then the nearest row
+int32_t host_medoid(const float *X, int64_t ld, int d, const int32_t *members, int64_t cnt)
+{
+    std::vector<double> mean(d, 0.0);
+    for (int64_t a = 0; a < cnt; ++a) {
+        const float *x = X + (int64_t)members[a] * ld;
+        for (int i = 0; i < d; ++i) mean[i] += (double)x[i];
+    }
+    for (int i = 0; i < d; ++i) mean[i] /= (double)cnt;
+    int32_t best = -1;
+    double bestd = INFINITY;
+    for (int64_t a = 0; a < cnt; ++a) {
+        const int32_t v = members[a];
+        const float *x = X + (int64_t)v * ld;
+        double acc = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double t = (double)x[i] - mean[i];
+            acc += t * t;
+        }
+        if (acc < bestd || (acc == bestd && v < best)) {
+            bestd = acc;
+            best = v;
+        }
+    }
+    return best;
+}
+
+int64_t mark_from(const std::vector<int32_t> &adj, int R, int64_t n, int32_t src, std::vector<uint8_t> &mark,
+                  std::vector<int32_t> &newly)
+{
+    newly.clear();
+    if (mark[src]) return 0;
+    mark[src] = 1;
+    newly.push_back(src);
+    for (size_t h = 0; h < newly.size(); ++h) {
+        const int32_t v = newly[h];
+        for (int r = 0; r < R; ++r) {
+            const int32_t u = adj[(int64_t)v * R + r];
+            if (u < 0 || u >= n || mark[u]) continue;
+            mark[u] = 1;
+            newly.push_back(u);
+        }
+    }
+    return (int64_t)newly.size();
+}
+
+int64_t uf_find(std::vector<int64_t> &par, int64_t x)
+{
+    while (par[x] != x) {
+        par[x] = par[par[x]];
+        x = par[x];
+    }
+    return x;
+}
+
+// device buffer that frees itself
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    hipError_t alloc(size_t count) { return hipMalloc(reinterpret_cast<void **>(&p), sizeof(T) * (count ? count : 1)); }
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+int medoid_device(const float *base, int64_t n, int d, int64_t ld, int32_t *out, hipStream_t s)
+{
+    const int64_t nchunks = (n + MED_CHUNK - 1) / MED_CHUNK;
+    const int64_t nblk = (n + 255) / 256;
+    DevBuf<double> part, mean, bestd;
+    DevBuf<int64_t> besti;
+    if (part.alloc(nchunks * d) != hipSuccess || mean.alloc(d) != hipSuccess || bestd.alloc(nblk) != hipSuccess ||
+        besti.alloc(nblk) != hipSuccess)
+        return set_error(SA_ENOMEM, "medoid: device allocation failed");
+    hipLaunchKernelGGL(colsum_partial, dim3((unsigned)nchunks), dim3(128), 0, s, base, n, d, ld, part.p);
+    hipLaunchKernelGGL(colsum_final, dim3((d + 127) / 128), dim3(128), 0, s, part.p, nchunks, d, n, mean.p);
+    hipLaunchKernelGGL(dist_to_mean, dim3((unsigned)nblk), dim3(256), 0, s, base, n, d, ld, mean.p, bestd.p, besti.p);
+    SA_HIP(hipGetLastError());
+    std::vector<double> hd(nblk);
+    std::vector<int64_t> hi(nblk);
+    SA_HIP(hipMemcpyAsync(hd.data(), bestd.p, sizeof(double) * nblk, hipMemcpyDeviceToHost, s));
+    SA_HIP(hipMemcpyAsync(hi.data(), besti.p, sizeof(int64_t) * nblk, hipMemcpyDeviceToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+    double bd = INFINITY;
+    int64_t bi = -1;
+    for (int64_t b = 0; b < nblk; ++b)
+        if (hd[b] < bd || (hd[b] == bd && hi[b] < bi)) {
+            bd = hd[b];
+            bi = hi[b];
+        }
+    *out = (int32_t)bi;
+    return SA_OK;
+}
+
+int prune_device(const float *base, int64_t n, int d, int64_t ld, int metric, const int32_t *cand, int kc, int R,
+                 int mode, int32_t *adj, hipStream_t s)
+{
+    if (n == 0) return SA_OK;
+    hipLaunchKernelGGL(prune_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, base, n, d, ld, metric, cand, kc,
+                       R, mode, adj);
+    SA_HIP(hipGetLastError());
+    return SA_OK;
+}
+
+int repair_device(const float *base, int64_t n, int d, int64_t ld, int metric, int32_t *adj_dev, int R,
+                  int32_t entry, int keep_local, int64_t *bridges_out, int64_t *ncomp_out, hipStream_t s)
+{
+    std::vector<int32_t> adj((size_t)n * R);
+    std::vector<float> X((size_t)n * ld);
+    SA_HIP(hipMemcpyAsync(adj.data(), adj_dev, sizeof(int32_t) * adj.size(), hipMemcpyDeviceToHost, s));
+    SA_HIP(hipMemcpyAsync(X.data(), base, sizeof(float) * X.size(), hipMemcpyDeviceToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+
+    // (1) weakly connected components, numbered by smallest member; medoid of each
+    std::vector<int64_t> par(n);
+    std::iota(par.begin(), par.end(), 0);
+    for (int64_t v = 0; v < n; ++v)
+        for (int r = 0; r < R; ++r) {
+            const int32_t u = adj[v * R + r];
+            if (u < 0) continue;
+            int64_t a = uf_find(par, v), b = uf_find(par, u);
+            if (a != b) {
+                if (a < b) par[b] = a;
+                else par[a] = b;
+            }
+        }
+    std::vector<int64_t> comp(n), root_comp(n, -1);
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t rt = uf_find(par, i);
+        if (root_comp[rt] < 0) root_comp[rt] = nc++;
+        comp[i] = root_comp[rt];
+    }
+    std::vector<int64_t> start(nc + 1, 0);
+    for (int64_t i = 0; i < n; ++i) start[comp[i] + 1]++;
+    for (int64_t c = 0; c < nc; ++c) start[c + 1] += start[c];
+    std::vector<int32_t> members(n);
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t i = 0; i < n; ++i) members[fill[comp[i]]++] = (int32_t)i;
+    }
+    std::vector<int32_t> rep(nc);
+    for (int64_t c = 0; c < nc; ++c) rep[c] = host_medoid(X.data(), ld, d, members.data() + start[c], start[c + 1] - start[c]);
+    if (ncomp_out) *ncomp_out = nc;
+
+    // (2) gateway rows
+    const int cap = R - keep_local;
+    if (nc > 1 && cap > 0) {
+        bool entry_is_rep = std::find(rep.begin(), rep.end(), entry) != rep.end();
+        const int64_t nsrc = nc + (entry_is_rep ? 0 : 1);
+        std::vector<int32_t> links((size_t)nsrc * cap, -1);
+        for (int64_t a = 0; a < nsrc; ++a) {
+            const int32_t v = a < nc ? rep[a] : entry;
+            struct C {
+                float d;
+                int32_t id;
+                bool used;
+            };
+            std::vector<C> cand;
+            cand.reserve(nc);
+            for (int64_t c = 0; c < nc; ++c) {
+                if (rep[c] == v) continue;
+                cand.push_back({host_dist(&X[(int64_t)v * ld], &X[(int64_t)rep[c] * ld], d, metric), rep[c], false});
+            }
+            std::sort(cand.begin(), cand.end(), [](const C &x, const C &y) { return key_less_host(x.d, x.id, y.d, y.id); });
+            int32_t *out = &links[(size_t)a * cap];
+            int kept = 0;
+            for (auto &c : cand) {
+                if (kept >= cap) break;
+                bool keep = true;
+                for (int x = 0; x < kept && keep; ++x)
+                    if (host_dist(&X[(int64_t)out[x] * ld], &X[(int64_t)c.id * ld], d, metric) < c.d) keep = false;
+                if (keep) {
+                    out[kept++] = c.id;
+                    c.used = true;
+                }
+            }
+            for (auto &c : cand) {
+                if (kept >= cap) break;
+                if (!c.used) out[kept++] = c.id;
+            }
+        }
+        for (int64_t a = 0; a < nsrc; ++a) {
+            const int32_t v = a < nc ? rep[a] : entry;
+            int32_t *rw = &adj[(int64_t)v * R];
+            const int32_t *lk = &links[(size_t)a * cap];
+            std::vector<int32_t> nr;
+            for (int r = 0; r < R && (int)nr.size() < keep_local; ++r) {
+                const int32_t u = rw[r];
+                if (u < 0) continue;
+                if (std::find(lk, lk + cap, u) != lk + cap) continue;
+                nr.push_back(u);
+            }
+            for (int x = 0; x < cap; ++x)
+                if (lk[x] >= 0) nr.push_back(lk[x]);
+            for (int r = 0; r < R; ++r) rw[r] = r < (int)nr.size() ? nr[r] : -1;
+        }
+    }
+
+    // (3) reachability: bridge every unreachable vertex, in id order, from the nearest
+    // reachable vertex with a free slot
+    std::vector<uint8_t> mark(n, 0);
+    std::vector<int32_t> newly;
+    mark_from(adj, R, n, entry, mark, newly);
+    std::vector<int32_t> deg(n);
+    for (int64_t v = 0; v < n; ++v) {
+        int c = 0;
+        for (int r = 0; r < R; ++r) c += adj[v * R + r] >= 0;
+        deg[v] = c;
+    }
+    int64_t added = 0;
+    int64_t first_unmarked = 0;
+    while (first_unmarked < n && mark[first_unmarked]) ++first_unmarked;
+    if (first_unmarked < n) {
+        DevBuf<uint8_t> dmask;
+        DevBuf<int32_t> ddeg, dlist;
+        DevBuf<unsigned long long> dres;
+        if (dmask.alloc(n) != hipSuccess || ddeg.alloc(n) != hipSuccess || dlist.alloc(n) != hipSuccess ||
+            dres.alloc(1) != hipSuccess)
+            return set_error(SA_ENOMEM, "repair: device allocation failed");
+        SA_HIP(hipMemcpyAsync(dmask.p, mark.data(), n, hipMemcpyHostToDevice, s));
+        SA_HIP(hipMemcpyAsync(ddeg.p, deg.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+        for (int64_t u = first_unmarked; u < n; ++u) {
+            if (mark[u]) continue;
+            hipLaunchKernelGGL(fill_u64, dim3(1), dim3(64), 0, s, dres.p, (unsigned long long)KEY_EMPTY);
+            hipLaunchKernelGGL(nearest_marked, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, base, n, d, ld,
+                               metric, dmask.p, ddeg.p, R, (int32_t)u, dres.p);
+            SA_HIP(hipGetLastError());
+            unsigned long long best;
+            SA_HIP(hipMemcpyAsync(&best, dres.p, sizeof(best), hipMemcpyDeviceToHost, s));
+            SA_HIP(hipStreamSynchronize(s));
+            if (best == KEY_EMPTY) return set_error(SA_ECAPACITY, "repair: no reachable vertex has a free slot");
+            const int32_t r = key_id(best);
+            adj[(int64_t)r * R + deg[r]] = (int32_t)u;
+            deg[r]++;
+            SA_HIP(hipMemcpyAsync(ddeg.p + r, &deg[r], sizeof(int32_t), hipMemcpyHostToDevice, s));
+            ++added;
+            mark_from(adj, R, n, (int32_t)u, mark, newly);
+            SA_HIP(hipMemcpyAsync(dlist.p, newly.data(), sizeof(int32_t) * newly.size(), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(set_marks, dim3((unsigned)((newly.size() + 255) / 256)), dim3(256), 0, s, dmask.p,
+                               dlist.p, (int64_t)newly.size());
+            SA_HIP(hipGetLastError());
+            SA_HIP(hipStreamSynchronize(s));
+        }
+    }
+    SA_HIP(hipMemcpyAsync(adj_dev, adj.data(), sizeof(int32_t) * adj.size(), hipMemcpyHostToDevice, s));
+    SA_HIP(hipStreamSynchronize(s));
+    if (bridges_out) *bridges_out = added;
+    return SA_OK;
+}
+
+}  // namespace sa

@@ -1,0 +1,80 @@
+// Internal declarations shared by the HIP sources of libspeedann (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/speedann.h"
+
+namespace sa {
+
+// ---------------------------------------------------------------- errors (host)
+
+int set_error(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+
+#define SA_HIP(call)                                   \
+    do {                                               \
+        hipError_t _e = (call);                        \
+        if (_e != hipSuccess) return hip_fail(_e, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------- keys
+// A list entry is the 64-bit key (ordered distance bits << 32 | id).  Ordering the
+// keys as unsigned integers orders entries by (distance, id): the float-to-unsigned map
+// below is monotone over all non-NaN floats, and -0 is folded into +0 first so that
+// equal distances compare equal and fall through to the id.
+
+constexpr uint64_t KEY_EMPTY = ~0ull;
+
+__host__ __device__ inline uint32_t float_to_ordered(float f)
+{
+    if (f == 0.0f) f = 0.0f;
+    uint32_t b;
+    __builtin_memcpy(&b, &f, 4);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__host__ __device__ inline float ordered_to_float(uint32_t o)
+{
+    uint32_t b = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+    float f;
+    __builtin_memcpy(&f, &b, 4);
+    return f;
+}
+
+__host__ __device__ inline uint64_t make_key(float dist, int32_t id)
+{
+    return ((uint64_t)float_to_ordered(dist) << 32) | (uint32_t)id;
+}
+
+__host__ __device__ inline int32_t key_id(uint64_t k) { return (int32_t)(uint32_t)(k & 0xFFFFFFFFu); }
+__host__ __device__ inline float key_dist(uint64_t k) { return ordered_to_float((uint32_t)(k >> 32)); }
+
+// ---------------------------------------------------------------- launchers
+
+int launch_knn(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq, int64_t ldq,
+               int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists, hipStream_t stream);
+
+struct SearchLaunch {
+    const float *vec;
+    int64_t ld, n;
+    int32_t d, metric;
+    const int32_t *adj;
+    int32_t R, entry;
+    const float *queries;
+    int64_t ldq, nq;
+    int32_t k, L, M;
+    sa_search_params p;
+    int32_t *ids;
+    float *dists;
+    sa_query_stats *stats;
+    void *workspace;
+    size_t ws_bytes;
+};
+
+size_t search_workspace_bytes(int64_t nq, int32_t L, int32_t M, const sa_search_params &p, int32_t R);
+int launch_search(const SearchLaunch &a, hipStream_t stream);
+
+}  // namespace sa

@@ -1,0 +1,78 @@
+"""C-ABI checks that need no GPU: the built library loads, exports every function the
+header declares, and rejects invalid arguments on the host before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "speedann.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sa_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2201_13007_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libspeedann.so is not built; run __graft_entry__.build()")
+    return binding
+
+
+def test_exports_match_header(B):
+    names = declared_functions()
+    assert "sa_search" in names and "sa_build_graph" in names and "sa_knn" in names
+    L = B.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(B.EXPORTS) == names
+
+
+def test_default_params(B):
+    p = B.SearchParams()
+    B.lib().sa_default_params(C.byref(p))
+    assert p.sync == 2 and abs(p.rho - 0.8) < 1e-7 and p.staged == 1 and p.static_I == 0
+
+
+def _err(B):
+    return B.lib().sa_last_error().decode()
+
+
+def test_validation_errors_without_device(B):
+    L = B.lib()
+    fake = 1 << 20   # an aligned non-null address; never dereferenced on these paths
+    out = C.c_void_p(0)
+    # index creation touches no device
+    assert L.sa_index_create(fake, 100, 30, 32, 0, fake, 16, 0, C.byref(out)) == -1
+    assert "multiple of 4" in _err(B)
+    assert L.sa_index_create(fake, 100, 32, 32, 0, fake, 65, 0, C.byref(out)) == -1
+    assert "R=65" in _err(B)
+    assert L.sa_index_create(fake, 100, 32, 32, 0, fake, 16, 100, C.byref(out)) == -1
+    assert "entry" in _err(B)
+    assert L.sa_index_create(fake, 100, 32, 32, 7, fake, 16, 0, C.byref(out)) == -1
+    assert L.sa_index_create(fake, 100, 32, 32, 0, fake, 16, 5, C.byref(out)) == 0
+    ix = out
+    p = B.SearchParams()
+    L.sa_default_params(C.byref(p))
+    # k > L, M > 16, L > 1024
+    for (k, Lq, M) in ((11, 10, 1), (10, 10, 17), (10, 2000, 1), (0, 10, 1)):
+        assert L.sa_search(ix, fake, 4, 32, k, Lq, M, C.byref(p), fake, fake, None, fake, 1 << 30, None) == -1
+    # a workspace that is too small is reported before any launch
+    assert L.sa_search_workspace_bytes(ix, 1000, 10, 64, 4, C.byref(p)) > 0
+    p.rho = float("nan")
+    assert L.sa_search(ix, fake, 4, 32, 10, 64, 4, C.byref(p), fake, fake, None, fake, 1 << 30, None) == -1
+    assert "rho" in _err(B)
+    L.sa_index_destroy(ix)
+    # exact kNN argument checks
+    assert L.sa_knn(fake, 10, 32, 32, fake, 3, 32, 0, 0, 0, fake, fake, None) == -1
+    assert L.sa_knn(fake, 10, 32, 32, fake, 3, 32, 300, 0, 0, fake, fake, None) == -1
+    assert L.sa_knn(fake + 4, 10, 32, 32, fake, 3, 32, 5, 0, 0, fake, fake, None) == -1
+    assert "aligned" in _err(B)
+    assert L.sa_prune(fake, 10, 32, 32, 0, fake, 65, 16, 1, fake, None) == -1
+    e = C.c_int32(0)
+    assert L.sa_build_graph(fake, 1, 32, 32, 0, 16, 16, 0, 0, 1, fake, C.byref(e), None, None, None) == -1

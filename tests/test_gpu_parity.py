@@ -1,0 +1,262 @@
+"""GPU parity: every C-ABI call against the CPU oracle on the same seeded inputs.
+
+Bar: ids, graph rows and counters bit-exact; distances bit-exact where the data make
+every partial sum exact (integer-valued sets), otherwise within 1e-5 relative.  The
+oracle and the GPU library share no code; inputs come from the generators only.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_13007_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2201_13007_amd import binding
+    binding.lib()
+    return binding
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def assert_dists(got, want, exact):
+    if exact:
+        np.testing.assert_array_equal(got, want)
+    else:
+        np.testing.assert_allclose(got, want, rtol=1e-5, atol=0)
+
+
+# ------------------------------------------------------------------ exact kNN
+
+def test_knn_tiny_float(B):
+    w = synth.tiny()
+    print("case: knn tiny 10000x32 k=16 exclude_self", flush=True)
+    ids, d = B.knn(dev(w.base), None, 16, exclude_self=True)
+    eids, ed = oracle.knn(w.base, w.base, 16, exclude_self=True)
+    np.testing.assert_array_equal(host(ids), eids)
+    np.testing.assert_array_equal(host(d), ed)
+    print("case: knn tiny queries k=10", flush=True)
+    ids, d = B.knn(dev(w.base), dev(w.queries), 10)
+    eids, ed = oracle.knn(w.base, w.queries, 10)
+    np.testing.assert_array_equal(host(ids), eids)
+    np.testing.assert_array_equal(host(d), ed)
+
+
+@pytest.mark.parametrize("k", [1, 7, 64, 100, 256])
+def test_knn_integer_ties_and_k(B, k):
+    # small integers: many exact distance ties, resolved by id
+    w = synth.integer_grid(3001, 8, 45, hi=4)
+    print(f"case: knn int-grid 3001x8 k={k}", flush=True)
+    ids, d = B.knn(dev(w.base), dev(w.queries), k)
+    eids, ed = oracle.knn(w.base, w.queries, k)
+    np.testing.assert_array_equal(host(ids), eids)
+    np.testing.assert_array_equal(host(d), ed)
+
+
+def test_knn_ip_and_short(B):
+    w = synth.deep_like(n=2000, nq=33)
+    print("case: knn ip 2000x96", flush=True)
+    ids, d = B.knn(dev(w.base), dev(w.queries), 10, metric="ip")
+    eids, ed = oracle.knn(w.base, w.queries, 10, metric="ip")
+    np.testing.assert_array_equal(host(ids), eids)
+    np.testing.assert_array_equal(host(d), ed)
+    # fewer base rows than k: padded with (-1, +inf)
+    ids, d = B.knn(dev(w.base[:5]), dev(w.queries), 8, metric="ip")
+    eids, ed = oracle.knn(w.base[:5], w.queries, 8, metric="ip")
+    np.testing.assert_array_equal(host(ids), eids)
+    np.testing.assert_array_equal(host(d), ed)
+
+
+# ------------------------------------------------------------------ graph construction
+
+def test_medoid(B):
+    for w in (synth.tiny(), synth.sift_like(n=20_000, nq=1)):
+        print(f"case: medoid {w.name}", flush=True)
+        assert B.medoid(dev(w.base)) == oracle.medoid(w.base)
+
+
+@pytest.mark.parametrize("mode", ["knn", "rng"])
+def test_prune(B, mode):
+    w = synth.sift_like(n=6000, nq=1)
+    cand, _ = oracle.knn(w.base, w.base, 64, exclude_self=True)
+    print(f"case: prune {mode} 6000x128 kc=64 R=32", flush=True)
+    got = host(B.prune(dev(w.base), dev(cand), 32, mode))
+    want = oracle.prune(w.base, cand, 32, mode)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_repair(B):
+    w = synth.sift_like(n=12_000, nq=1)
+    cand, _ = oracle.knn(w.base, w.base, 64, exclude_self=True)
+    adj0 = oracle.prune(w.base, cand, 32, "rng")
+    entry = oracle.medoid(w.base)
+    want = adj0.copy()
+    wb, wc = oracle.repair(w.base, want, entry, keep_local=1)
+    print(f"case: repair 12000x128 bridges={wb} comps={wc}", flush=True)
+    g = dev(adj0)
+    gb, gc = B.repair(dev(w.base), g, entry, keep_local=1)
+    np.testing.assert_array_equal(host(g), want)
+    assert (gb, gc) == (wb, wc)
+    assert oracle.reachable(want, entry)[0] == w.base.shape[0]
+
+
+def test_build_graph_tiny(B):
+    w = synth.tiny()
+    print("case: build_graph tiny (16-NN, no repair)", flush=True)
+    adj, entry, _ = B.build_graph(dev(w.base), 16, 16, "knn", do_repair=False)
+    eadj, eentry, _ = oracle.build_graph(w.base, 16, 16, "knn", do_repair=False)
+    assert entry == eentry
+    np.testing.assert_array_equal(host(adj), eadj)
+
+
+# ------------------------------------------------------------------ search
+
+def run_both(B, base, adj, entry, queries, k, L, M, sync="adaptive", static_I=0, rho=0.8, staged=True,
+             metric="l2", **kw):
+    ix = B.Index(dev(base), dev(adj), entry, metric=metric)
+    r = ix.search(dev(queries), k, L, M, stats=True, sync=sync, static_I=static_I, rho=rho, staged=staged, **kw)
+    gids, gd, gst = host(r.ids), host(r.dists), host(r.stats)
+    eids, ed, est = oracle.speedann(base, adj, entry, queries, k, L, M, sync=sync, static_I=static_I, rho=rho,
+                                    staged=staged, metric=metric)
+    return (gids, gd, gst), (eids, ed, est)
+
+
+def assert_search_equal(g, e, exact, check_counters=True, label=""):
+    gids, gd, gst = g
+    eids, ed, est = e
+    bad = np.nonzero((gids != eids).any(1))[0]
+    assert bad.size == 0, f"{label}: ids differ for queries {bad[:10].tolist()}: gpu {gids[bad[0]].tolist()} " \
+                          f"oracle {eids[bad[0]].tolist()}"
+    assert_dists(gd, ed, exact)
+    if check_counters:
+        for j, name in enumerate(["global_steps", "substeps", "expansions", "dist_comps", "merges"]):
+            np.testing.assert_array_equal(gst[:, j], est[name], err_msg=f"{label} {name}")
+    assert (gst[:, 5] & ~4 == 0).all(), f"{label}: flags {np.unique(gst[:, 5])}"
+
+
+@pytest.fixture(scope="module")
+def tiny_setup():
+    w = synth.tiny()
+    adj, entry, _ = oracle.build_graph(w.base, 16, 16, "knn", do_repair=False)
+    return w, adj, entry
+
+
+@pytest.mark.parametrize("M", [1, 4])
+@pytest.mark.parametrize("sync,staged", [("adaptive", True), ("adaptive", False), ("bsp", False), ("static", True)])
+def test_search_tiny(B, tiny_setup, M, sync, staged):
+    w, adj, entry = tiny_setup
+    print(f"case: search tiny M={M} sync={sync} staged={staged}", flush=True)
+    g, e = run_both(B, w.base, adj, entry, w.queries, 10, 64, M, sync=sync, staged=staged, static_I=3)
+    assert_search_equal(g, e, exact=False, label=f"tiny M={M} {sync}")
+
+
+@pytest.fixture(scope="module")
+def sift_setup():
+    w = synth.sift_like(n=20_000, nq=150)
+    adj, entry, info = oracle.build_graph(w.base, 64, 32, "rng", do_repair=True)
+    return w, adj, entry
+
+
+@pytest.mark.parametrize("L", [32, 100, 256])
+@pytest.mark.parametrize("M", [1, 2, 8, 16])
+def test_search_sift_shaped(B, sift_setup, L, M):
+    w, adj, entry = sift_setup
+    for sync, staged, rho in (("adaptive", True, 0.8), ("bsp", False, 0.0), ("static", False, 0.0)):
+        print(f"case: search sift-20k L={L} M={M} sync={sync} staged={staged}", flush=True)
+        g, e = run_both(B, w.base, adj, entry, w.queries, 10, L, M, sync=sync, staged=staged, rho=rho, static_I=4)
+        assert_search_equal(g, e, exact=True, label=f"sift L={L} M={M} {sync}")
+
+
+def test_search_golden_line(B):
+    with open(os.path.join(GOLDEN, "line10_adaptive.json")) as f:
+        gl = json.load(f)
+    base = np.array(gl["coords"], np.float32)[:, None]
+    adj = np.array(gl["adj"], np.int32)
+    q = np.array([[gl["query"]]], np.float32)
+    for c in gl["cases"]:
+        if c["algo"] != "speedann":
+            continue
+        print(f"case: golden line {c['name']}", flush=True)
+        ix = B.Index(dev(base), dev(adj), gl["entry"])
+        r = ix.search(dev(q), gl["k"], gl["L"], c["T"], stats=True, sync=c["sync"], rho=c["rho"],
+                      staged=c["staged"], static_I=c.get("static_I", 0))
+        assert host(r.ids)[0].tolist() == c["ids"]
+        assert host(r.dists)[0].tolist() == c["dists"]
+        st = host(r.stats)[0]
+        assert st[:5].tolist() == [c["global_steps"], c["substeps"], c["expansions"], c["dist_comps"], c["merges"]]
+
+
+def test_search_edge_cases(B):
+    w = synth.integer_grid(500, 8, 20, hi=5)
+    rng = np.random.default_rng(11)
+    adj = rng.integers(-1, 500, size=(500, 6)).astype(np.int32)
+    for i in range(500):
+        row = []
+        for u in adj[i]:
+            if u >= 0 and u not in row:
+                row.append(int(u))
+        adj[i] = row + [-1] * (6 - len(row))
+    cases = [dict(k=1, L=1, M=1), dict(k=5, L=5, M=3), dict(k=10, L=500, M=16), dict(k=10, L=1024, M=5),
+             dict(k=20, L=20, M=16, sync="bsp", staged=False), dict(k=3, L=40, M=7, sync="static", static_I=2)]
+    for c in cases:
+        print(f"case: edge {c}", flush=True)
+        g, e = run_both(B, w.base, adj, 3, w.queries, **c)
+        assert_search_equal(g, e, exact=True, label=str(c))
+    # an entry with no out-edges: the result is the entry alone, padded
+    adj2 = adj.copy()
+    adj2[3] = -1
+    g, e = run_both(B, w.base, adj2, 3, w.queries, 4, 8, 2)
+    assert_search_equal(g, e, exact=True, label="isolated entry")
+    assert (g[0][:, 1:] == -1).all() and np.isinf(g[1][:, 1:]).all()
+
+
+def test_search_visited_spill(B, sift_setup):
+    """A tiny LDS visited table forces every query onto the workspace table; the
+    results must not change."""
+    w, adj, entry = sift_setup
+    print("case: spill lds_hash_slots=1024 M=8 L=256", flush=True)
+    g, e = run_both(B, w.base, adj, entry, w.queries, 10, 256, 8, lds_hash_slots=1024)
+    assert_search_equal(g, e, exact=True, label="spill")
+    assert (g[2][:, 5] & 4).any()
+
+
+def test_search_capacity_and_max_steps_flags(B, sift_setup):
+    w, adj, entry = sift_setup
+    ix = B.Index(dev(w.base), dev(adj), entry)
+    print("case: capacity flag (tiny workspace table)", flush=True)
+    r = ix.search(dev(w.queries[:8]), 10, 256, 4, stats=True, lds_hash_slots=512, ws_hash_slots=512)
+    st = host(r.stats)
+    assert (st[:, 5] & 2).all()
+    print("case: max_substeps flag", flush=True)
+    r = ix.search(dev(w.queries[:8]), 10, 128, 2, stats=True, max_substeps=5)
+    st = host(r.stats)
+    assert (st[:, 5] & 1).all() and (st[:, 1] == 5).all()
+    eids, ed, _ = oracle.speedann(w.base, adj, entry, w.queries[:8], 10, 128, 2, max_substeps=5)
+    np.testing.assert_array_equal(host(r.ids), eids)
+
+
+def test_search_ip_deep_shaped(B):
+    w = synth.deep_like(n=8000, nq=60)
+    adj, entry, _ = oracle.build_graph(w.base, 32, 24, "rng", do_repair=True, metric="ip")
+    for M in (1, 4):
+        print(f"case: search deep-8k ip M={M}", flush=True)
+        g, e = run_both(B, w.base, adj, entry, w.queries, 10, 64, M, metric="ip", rho=0.9)
+        assert_search_equal(g, e, exact=False, label=f"ip M={M}")
