@@ -118,24 +118,37 @@ int sa_medoid(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t *
 int sa_prune(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, const int32_t *cand_dev,
              int32_t kc, int32_t R, int32_t prune, int32_t *adj_dev, void *hip_stream);
 
+/* Reverse edges, in place (synchronous): with the graph as it stands, every vertex c
+ * appends to its row the sources p of its in-edges (p -> c) that the row does not hold
+ * yet, in key order (d(c, p), p), while the row has fewer than R entries.  All rows read
+ * the graph as it was before any append.  *added_out (if not NULL) gets the count. */
+int sa_reverse_edges(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, int32_t *adj_dev,
+                     int32_t R, int64_t *added_out, void *hip_stream);
+
 /* Connectivity repair of adj_dev in place (synchronous; copies the graph to the host):
- * (1) weakly connected components, each with its medoid as representative; (2) every
- * representative and the entry get a new row: their first keep_local edges, then up to
- * R - keep_local links to other representatives chosen by the relative-neighbourhood
- * rule and filled with the nearest ones; (3) in increasing id order every vertex not
- * reachable from the entry gets an edge from the nearest reachable vertex with a free
- * slot.  Writes the number of (3) edges and components to the outputs when not NULL.
+ * (1) weakly connected components, each with its medoid as representative;
+ * (2) gateway rows: every representative (keeping its first keep_local edges), the entry
+ *     and the hubs - the `hubs` - 1 other vertices nearest to the mean of all rows,
+ *     representatives excepted (keeping hub_keep_local edges each) - get a new row: the
+ *     kept edges, then links to other representatives chosen by the relative-
+ *     neighbourhood rule over all of them in key order and filled with the nearest
+ *     ones.  On clustered data this is what lets a search that starts at the medoid
+ *     leave the medoid's cluster;
+ * (3) in increasing id order every vertex not reachable from the entry gets an edge from
+ *     the nearest reachable vertex with a free slot.
+ * Writes the number of (3) edges and of components to the outputs when not NULL.
  * SA_ECAPACITY if (3) finds no reachable vertex with a free slot. */
 int sa_repair(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, int32_t *adj_dev,
-              int32_t R, int32_t entry, int32_t keep_local, int64_t *bridges_out, int64_t *components_out,
-              void *hip_stream);
+              int32_t R, int32_t entry, int32_t keep_local, int32_t hubs, int32_t hub_keep_local,
+              int64_t *bridges_out, int64_t *components_out, void *hip_stream);
 
 /* Whole pipeline: entry = sa_medoid; candidates = sa_knn(knn_k, exclude_self);
- * adj = sa_prune; if repair, sa_repair(keep_local).  Synchronous.  Allocates its
+ * adj = sa_prune; if repair, sa_reverse_edges then sa_repair(keep_local, hubs, hub_keep_local).  Synchronous.  Allocates its
  * temporaries with hipMalloc and frees them before returning. */
 int sa_build_graph(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, int32_t knn_k,
-                   int32_t R, int32_t prune, int32_t repair, int32_t keep_local, int32_t *adj_dev,
-                   int32_t *entry_out, int64_t *bridges_out, int64_t *components_out, void *hip_stream);
+                   int32_t R, int32_t prune, int32_t repair, int32_t keep_local, int32_t hubs,
+                   int32_t hub_keep_local, int32_t *adj_dev, int32_t *entry_out, int64_t *bridges_out,
+                   int64_t *components_out, void *hip_stream);
 
 /* ------------------------------------------------------------------ the search */
 

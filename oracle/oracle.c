@@ -509,22 +509,75 @@ static int64_t uf_find(int64_t *par, int64_t x)
     return x;
 }
 
+/* Reverse edges: with the pruned graph as it stands, every vertex c appends to its row
+ * the sources p of its in-edges (p -> c) that its row does not hold yet, in key order
+ * (d(c, p), p), while the row has fewer than R entries.  All rows read the graph as it
+ * was before any append.  Returns the number of edges added. */
+int64_t or_reverse_edges(const float *base, int64_t n, int d, int64_t ld, int metric, int32_t *adj, int R)
+{
+    int32_t *snap = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)R);
+    memcpy(snap, adj, sizeof(int32_t) * (size_t)n * (size_t)R);
+    int64_t *start = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t p = 0; p < n; ++p)
+        for (int r = 0; r < R; ++r) if (snap[p * R + r] >= 0) start[snap[p * R + r] + 1]++;
+    for (int64_t c = 0; c < n; ++c) start[c + 1] += start[c];
+    int32_t *src = (int32_t *)malloc(sizeof(int32_t) * (size_t)(start[n] > 0 ? start[n] : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t c = 0; c < n; ++c) fill[c] = start[c];
+    for (int64_t p = 0; p < n; ++p)
+        for (int r = 0; r < R; ++r) {
+            int32_t c = snap[p * R + r];
+            if (c >= 0) src[fill[c]++] = (int32_t)p;
+        }
+    int64_t added = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : added)
+    for (int64_t c = 0; c < n; ++c) {
+        int64_t cnt = start[c + 1] - start[c];
+        if (cnt == 0) continue;
+        int deg = 0;
+        for (int r = 0; r < R; ++r) if (snap[c * R + r] >= 0) deg++;
+        if (deg >= R) continue;
+        entry *e = (entry *)malloc(sizeof(entry) * (size_t)cnt);
+        for (int64_t a = 0; a < cnt; ++a) {
+            int32_t p = src[start[c] + a];
+            e[a].dist = or_distance(row(base, c, ld), row(base, p, ld), d, metric);
+            e[a].id = p;
+            e[a].state = 0;
+        }
+        sort_entries(e, cnt);
+        for (int64_t a = 0; a < cnt && deg < R; ++a) {
+            int dup = 0;
+            for (int r = 0; r < deg; ++r) if (adj[c * R + r] == e[a].id) { dup = 1; break; }
+            if (dup) continue;
+            adj[c * R + deg] = e[a].id;
+            deg++;
+            added++;
+        }
+        free(e);
+    }
+    free(snap); free(start); free(src); free(fill);
+    return added;
+}
+
 /* Connectivity repair, in three parts, all deterministic:
  *  (1) components: the weakly connected components of the pruned graph, numbered by
  *      their smallest member id; each gets a representative, its medoid;
- *  (2) gateway rows: every representative, then the entry vertex (unless it is a
- *      representative), gets a new row: its first keep_local pruned edges, then links
- *      to other representatives.  The links are chosen with the relative-neighbourhood
- *      rule over all other representatives in key order (distance to the source, id),
- *      up to R - keep_local of them, and the remaining slots are filled with the
- *      nearest representatives not yet linked;
+ *  (2) gateway rows: every representative (keeping keep_local of its edges), the entry
+ *      and the hubs - the `hubs` vertices nearest to the mean of all rows (double
+ *      precision, key (distance, id)), representatives excepted (keeping hub_keep_local
+ *      edges each) - get a new row: its first kept edges that are not links, then
+ *      links to other representatives.  The links are chosen with the
+ *      relative-neighbourhood rule over all other representatives in key order
+ *      (distance to the source, id), up to R - kept of them, and the remaining slots
+ *      are filled with the nearest representatives not yet linked.  Every row is
+ *      computed from the graph as it was before this part;
  *  (3) reachability: in increasing id order, every vertex u not reachable from the entry
  *      gets an edge from the reachable vertex nearest to it (key (distance, id)) among
  *      those with a free slot; then everything reachable from u is marked.
  * Returns the number of edges added in (3), or -1 if (3) found no vertex with a free
  * slot.  ncomp_out receives the component count. */
 int64_t or_repair(const float *base, int64_t n, int d, int64_t ld, int metric, int32_t *adj, int R,
-                  int32_t entry_id, int keep_local, int64_t *ncomp_out)
+                  int32_t entry_id, int keep_local, int hubs, int hub_keep_local, int64_t *ncomp_out)
 {
     int64_t *par = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     for (int64_t i = 0; i < n; ++i) par[i] = i;
@@ -557,59 +610,93 @@ int64_t or_repair(const float *base, int64_t n, int d, int64_t ld, int metric, i
     for (int64_t c = 0; c < nc; ++c)
         rep[c] = (int32_t)medoid_of(base, ld, d, members + start[c], start[c + 1] - start[c]);
 
-    /* (2) gateway rows */
-    int cap = R - keep_local;
-    if (nc > 1 && cap > 0) {
-        int is_rep = 0;
-        for (int64_t c = 0; c < nc; ++c) if (rep[c] == entry_id) is_rep = 1;
-        int64_t nsrc = nc + (is_rep ? 0 : 1);
-        int32_t *links = (int32_t *)malloc(sizeof(int32_t) * (size_t)nsrc * (size_t)cap);
-#pragma omp parallel for schedule(dynamic, 1)
-        for (int64_t a = 0; a < nsrc; ++a) {
-            int32_t v = a < nc ? rep[a] : entry_id;
-            /* candidates: every other representative, sorted by key */
-            entry *cand = (entry *)malloc(sizeof(entry) * (size_t)nc);
-            int64_t ncand = 0;
-            for (int64_t c = 0; c < nc; ++c) {
-                if (rep[c] == v) continue;
-                cand[ncand].dist = or_distance(row(base, v, ld), row(base, rep[c], ld), d, metric);
-                cand[ncand].id = rep[c]; cand[ncand].state = 0;
-                ++ncand;
-            }
-            sort_entries(cand, ncand);
-            int32_t *out = links + a * cap;
-            int kept = 0;
-            for (int64_t j = 0; j < ncand && kept < cap; ++j) {
-                int keep = 1;
-                for (int x = 0; x < kept; ++x) {
-                    float dsc = or_distance(row(base, out[x], ld), row(base, cand[j].id, ld), d, metric);
-                    if (dsc < cand[j].dist) { keep = 0; break; }
-                }
-                if (keep) { out[kept++] = cand[j].id; cand[j].state = 1; }
-            }
-            for (int64_t j = 0; j < ncand && kept < cap; ++j)
-                if (cand[j].state == 0) out[kept++] = cand[j].id;
-            for (int x = kept; x < cap; ++x) out[x] = -1;
-            free(cand);
-        }
-        /* rewrite the rows: first keep_local pruned edges not among the links, then links */
-        for (int64_t a = 0; a < nsrc; ++a) {
-            int32_t v = a < nc ? rep[a] : entry_id;
-            int32_t *rw = adj + (int64_t)v * R;
-            int32_t newrow[256];
+    /* (2) gateway rows: sources are the representatives, then the entry and the other
+     * hubs (vertices nearest to the mean, representatives excepted) */
+    uint8_t *is_rep = (uint8_t *)calloc((size_t)n, 1);
+    for (int64_t c = 0; c < nc; ++c) is_rep[rep[c]] = 1;
+    int64_t nhub = 0;
+    int32_t *hub = (int32_t *)malloc(sizeof(int32_t) * (size_t)(hubs > 0 ? hubs + 1 : 1));
+    if (nc > 1) {
+        if (!is_rep[entry_id]) hub[nhub++] = entry_id;
+        if (hubs > 1) {
+            double *mean = (double *)calloc((size_t)d, sizeof(double));
+            for (int64_t v = 0; v < n; ++v)
+                for (int i = 0; i < d; ++i) mean[i] += (double)row(base, v, ld)[i];
+            for (int i = 0; i < d; ++i) mean[i] /= (double)n;
+            /* the hubs smallest keys (distance to the mean, id) by repeated insertion */
+            double *hd = (double *)malloc(sizeof(double) * (size_t)hubs);
+            int32_t *hi = (int32_t *)malloc(sizeof(int32_t) * (size_t)hubs);
             int cnt = 0;
-            for (int r = 0; r < R && cnt < keep_local; ++r) {
-                int32_t u = rw[r];
-                if (u < 0) continue;
-                int dup = 0;
-                for (int x = 0; x < cap; ++x) if (links[a * cap + x] == u) dup = 1;
-                if (!dup) newrow[cnt++] = u;
+            for (int64_t v = 0; v < n; ++v) {
+                if (is_rep[v] || v == entry_id) continue;
+                double acc = 0.0;
+                for (int i = 0; i < d; ++i) { double t = (double)row(base, v, ld)[i] - mean[i]; acc += t * t; }
+                int limit = hubs - 1;
+                if (cnt == limit && !(acc < hd[limit - 1] || (acc == hd[limit - 1] && v < hi[limit - 1]))) continue;
+                int pos = cnt < limit ? cnt : limit - 1;
+                while (pos > 0 && (acc < hd[pos - 1] || (acc == hd[pos - 1] && v < hi[pos - 1]))) {
+                    hd[pos] = hd[pos - 1]; hi[pos] = hi[pos - 1]; --pos;
+                }
+                hd[pos] = acc; hi[pos] = (int32_t)v;
+                if (cnt < limit) ++cnt;
             }
-            for (int x = 0; x < cap; ++x) if (links[a * cap + x] >= 0) newrow[cnt++] = links[a * cap + x];
-            for (int r = 0; r < R; ++r) rw[r] = r < cnt ? newrow[r] : -1;
+            for (int j = 0; j < cnt; ++j) hub[nhub++] = hi[j];
+            free(mean); free(hd); free(hi);
         }
-        free(links);
     }
+    int64_t nsrc = nc > 1 ? nc + nhub : 0;
+    int32_t *links = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nsrc > 0 ? nsrc : 1) * (size_t)R);
+    int *kept_local = (int *)malloc(sizeof(int) * (size_t)(nsrc > 0 ? nsrc : 1));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t a = 0; a < nsrc; ++a) {
+        int32_t v = a < nc ? rep[a] : hub[a - nc];
+        int kl = a < nc ? keep_local : hub_keep_local;
+        int cap = R - kl;
+        kept_local[a] = kl;
+        int32_t *out = links + a * R;
+        for (int x = 0; x < R; ++x) out[x] = -1;
+        if (cap <= 0) continue;
+        /* candidates: every other representative, sorted by key */
+        entry *cand = (entry *)malloc(sizeof(entry) * (size_t)nc);
+        int64_t ncand = 0;
+        for (int64_t c = 0; c < nc; ++c) {
+            if (rep[c] == v) continue;
+            cand[ncand].dist = or_distance(row(base, v, ld), row(base, rep[c], ld), d, metric);
+            cand[ncand].id = rep[c]; cand[ncand].state = 0;
+            ++ncand;
+        }
+        sort_entries(cand, ncand);
+        int kept = 0;
+        for (int64_t j = 0; j < ncand && kept < cap; ++j) {
+            int keep = 1;
+            for (int x = 0; x < kept; ++x) {
+                float dsc = or_distance(row(base, out[x], ld), row(base, cand[j].id, ld), d, metric);
+                if (dsc < cand[j].dist) { keep = 0; break; }
+            }
+            if (keep) { out[kept++] = cand[j].id; cand[j].state = 1; }
+        }
+        for (int64_t j = 0; j < ncand && kept < cap; ++j)
+            if (cand[j].state == 0) out[kept++] = cand[j].id;
+        free(cand);
+    }
+    /* rewrite the rows: first kept edges not among the links, then the links */
+    for (int64_t a = 0; a < nsrc; ++a) {
+        int32_t v = a < nc ? rep[a] : hub[a - nc];
+        int32_t *rw = adj + (int64_t)v * R;
+        int32_t newrow[256];
+        int cnt = 0;
+        const int32_t *lk = links + a * R;
+        for (int r = 0; r < R && cnt < kept_local[a]; ++r) {
+            int32_t u = rw[r];
+            if (u < 0) continue;
+            int dup = 0;
+            for (int x = 0; x < R; ++x) if (lk[x] == u) dup = 1;
+            if (!dup) newrow[cnt++] = u;
+        }
+        for (int x = 0; x < R; ++x) if (lk[x] >= 0) newrow[cnt++] = lk[x];
+        for (int r = 0; r < R; ++r) rw[r] = r < cnt ? newrow[r] : -1;
+    }
+    free(links); free(kept_local); free(hub); free(is_rep);
 
     /* (3) reachability */
     uint8_t *mark = (uint8_t *)calloc((size_t)n, 1);

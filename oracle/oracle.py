@@ -66,9 +66,11 @@ def lib():
         L.or_medoid.restype = i64
         L.or_prune.argtypes = [f32p, i64, C.c_int, i64, C.c_int, i32p, C.c_int, C.c_int, C.c_int, i32p]
         L.or_prune.restype = None
-        L.or_repair.argtypes = [f32p, i64, C.c_int, i64, C.c_int, i32p, C.c_int, i32, C.c_int,
+        L.or_repair.argtypes = [f32p, i64, C.c_int, i64, C.c_int, i32p, C.c_int, i32, C.c_int, C.c_int, C.c_int,
                                 C.POINTER(C.c_int64)]
         L.or_repair.restype = i64
+        L.or_reverse_edges.argtypes = [f32p, i64, C.c_int, i64, C.c_int, i32p, C.c_int]
+        L.or_reverse_edges.restype = i64
         L.or_reachable.argtypes = [i32p, C.c_int, i64, i32, u8p]
         L.or_reachable.restype = i64
         _lib = L
@@ -152,17 +154,31 @@ def prune(base, cand, R, mode="rng", metric="l2"):
     return adj
 
 
-def repair(base, adj, entry, keep_local=1, metric="l2"):
+def default_hubs(n: int) -> int:
+    return max(1, n // 256)
+
+
+def repair(base, adj, entry, keep_local=1, metric="l2", hubs=None, hub_keep_local=4):
     """Connectivity repair in place; returns (bridges added, component count)."""
     base = _f32(base)
     assert adj.dtype == np.int32 and adj.flags.c_contiguous
     n, d = base.shape
+    if hubs is None:
+        hubs = default_hubs(n)
     nc = C.c_int64(0)
     added = lib().or_repair(base, n, d, d, _metric(metric), adj, adj.shape[1], int(entry), int(keep_local),
-                            C.byref(nc))
+                            int(hubs), int(hub_keep_local), C.byref(nc))
     if added < 0:
         raise RuntimeError("repair: no reachable vertex has a free slot")
     return int(added), int(nc.value)
+
+
+def reverse_edges(base, adj, metric="l2"):
+    """Adds reverse edges in place (see oracle.c); returns the number added."""
+    base = _f32(base)
+    assert adj.dtype == np.int32 and adj.flags.c_contiguous
+    n, d = base.shape
+    return int(lib().or_reverse_edges(base, n, d, d, _metric(metric), adj, adj.shape[1]))
 
 
 def reachable(adj, entry):
@@ -173,16 +189,21 @@ def reachable(adj, entry):
     return int(cnt), mark.astype(bool)
 
 
-def build_graph(base, knn_k, R, prune_mode="rng", do_repair=True, keep_local=1, metric="l2"):
-    """Exact knn_k-NN candidates, row pruning to R, medoid entry, optional repair.
-    Returns (adj, entry, info)."""
+def build_graph(base, knn_k, R, prune_mode="rng", do_repair=True, keep_local=1, metric="l2", reverse=None,
+                hubs=None, hub_keep_local=4):
+    """Exact knn_k-NN candidates, row pruning to R, medoid entry; with do_repair, reverse
+    edges (unless reverse=False) and the connectivity repair.  Returns (adj, entry, info)."""
     base = _f32(base)
     entry = medoid(base)
     cand, _ = knn(base, base, knn_k, metric, exclude_self=True)
     adj = prune(base, cand, R, prune_mode, metric)
-    info = {"bridges": 0, "components": None}
+    info = {"bridges": 0, "components": None, "reverse": 0}
+    if reverse is None:
+        reverse = do_repair
+    if reverse:
+        info["reverse"] = reverse_edges(base, adj, metric)
     if do_repair:
-        info["bridges"], info["components"] = repair(base, adj, entry, keep_local, metric)
+        info["bridges"], info["components"] = repair(base, adj, entry, keep_local, metric, hubs, hub_keep_local)
     return adj, entry, info
 
 

@@ -19,8 +19,8 @@ SA_L2, SA_IP = 0, 1
 SYNC = {"bsp": 0, "static": 1, "adaptive": 2}
 QFLAG_MAX_STEPS, QFLAG_CAPACITY, QFLAG_SPILLED = 1, 2, 4
 
-EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_medoid", "sa_prune", "sa_repair",
-           "sa_build_graph", "sa_index_create", "sa_index_destroy", "sa_search_workspace_bytes", "sa_search"]
+EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_medoid", "sa_prune", "sa_reverse_edges",
+           "sa_repair", "sa_build_graph", "sa_index_create", "sa_index_destroy", "sa_search_workspace_bytes", "sa_search"]
 
 
 class SearchParams(C.Structure):
@@ -53,17 +53,18 @@ def lib():
         L.sa_knn.argtypes = [vp, i64, i32, i64, vp, i64, i64, i32, i32, i32, vp, vp, vp]
         L.sa_medoid.argtypes = [vp, i64, i32, i64, C.POINTER(C.c_int32), vp]
         L.sa_prune.argtypes = [vp, i64, i32, i64, i32, vp, i32, i32, i32, vp, vp]
-        L.sa_repair.argtypes = [vp, i64, i32, i64, i32, vp, i32, i32, i32, C.POINTER(C.c_int64),
+        L.sa_reverse_edges.argtypes = [vp, i64, i32, i64, i32, vp, i32, C.POINTER(C.c_int64), vp]
+        L.sa_repair.argtypes = [vp, i64, i32, i64, i32, vp, i32, i32, i32, i32, i32, C.POINTER(C.c_int64),
                                 C.POINTER(C.c_int64), vp]
-        L.sa_build_graph.argtypes = [vp, i64, i32, i64, i32, i32, i32, i32, i32, i32, vp, C.POINTER(C.c_int32),
-                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
+        L.sa_build_graph.argtypes = [vp, i64, i32, i64, i32, i32, i32, i32, i32, i32, i32, i32, vp,
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
         L.sa_index_create.argtypes = [vp, i64, i32, i64, i32, vp, i32, i32, C.POINTER(vp)]
         L.sa_index_destroy.argtypes = [vp]
         L.sa_index_destroy.restype = None
         L.sa_search_workspace_bytes.argtypes = [vp, i64, i32, i32, i32, C.POINTER(SearchParams)]
         L.sa_search_workspace_bytes.restype = sz
         L.sa_search.argtypes = [vp, vp, i64, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp, sz, vp]
-        for name in ("sa_knn", "sa_medoid", "sa_prune", "sa_repair", "sa_build_graph", "sa_index_create",
+        for name in ("sa_knn", "sa_medoid", "sa_prune", "sa_reverse_edges", "sa_repair", "sa_build_graph", "sa_index_create",
                      "sa_search"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -136,27 +137,47 @@ def prune(base: torch.Tensor, cand: torch.Tensor, R: int, mode="rng", metric="l2
     return adj
 
 
-def repair(base: torch.Tensor, adj: torch.Tensor, entry: int, keep_local=1, metric="l2", stream=None):
+def reverse_edges(base: torch.Tensor, adj: torch.Tensor, metric="l2", stream=None) -> int:
+    """Reverse-edge insertion in place; returns the number of edges added."""
+    base = pad_dim(_mat(base, "base"))
+    assert adj.dtype == torch.int32 and adj.is_contiguous()
+    a = C.c_int64(0)
+    _check(lib().sa_reverse_edges(base.data_ptr(), base.shape[0], base.shape[1], base.stride(0), _metric(metric),
+                                  adj.data_ptr(), adj.shape[1], C.byref(a), _stream(stream)), "sa_reverse_edges")
+    return int(a.value)
+
+
+def default_hubs(n: int) -> int:
+    """Hub count of the repair: one per 256 vertices."""
+    return max(1, n // 256)
+
+
+def repair(base: torch.Tensor, adj: torch.Tensor, entry: int, keep_local=1, metric="l2", hubs=None,
+           hub_keep_local=4, stream=None):
     """Connectivity repair of adj in place; returns (bridges, components)."""
     base = pad_dim(_mat(base, "base"))
     assert adj.dtype == torch.int32 and adj.is_contiguous()
+    if hubs is None:
+        hubs = default_hubs(base.shape[0])
     b, c = C.c_int64(0), C.c_int64(0)
     _check(lib().sa_repair(base.data_ptr(), base.shape[0], base.shape[1], base.stride(0), _metric(metric),
-                           adj.data_ptr(), adj.shape[1], int(entry), int(keep_local), C.byref(b), C.byref(c),
-                           _stream(stream)), "sa_repair")
+                           adj.data_ptr(), adj.shape[1], int(entry), int(keep_local), int(hubs), int(hub_keep_local),
+                           C.byref(b), C.byref(c), _stream(stream)), "sa_repair")
     return int(b.value), int(c.value)
 
 
 def build_graph(base: torch.Tensor, knn_k: int, R: int, prune_mode="rng", do_repair=True, keep_local=1,
-                metric="l2", stream=None):
+                metric="l2", hubs=None, hub_keep_local=4, stream=None):
     """Returns (adj, entry, info) built on the GPU."""
     base = pad_dim(_mat(base, "base"))
     n = base.shape[0]
+    if hubs is None:
+        hubs = default_hubs(n)
     adj = torch.empty((n, R), dtype=torch.int32, device=base.device)
     entry, b, c = C.c_int32(0), C.c_int64(0), C.c_int64(0)
     _check(lib().sa_build_graph(base.data_ptr(), n, base.shape[1], base.stride(0), _metric(metric), knn_k, R,
                                 {"knn": 0, "rng": 1}[prune_mode], int(bool(do_repair)), int(keep_local),
-                                adj.data_ptr(), C.byref(entry), C.byref(b), C.byref(c), _stream(stream)),
+                                int(hubs), int(hub_keep_local), adj.data_ptr(), C.byref(entry), C.byref(b), C.byref(c), _stream(stream)),
            "sa_build_graph")
     return adj, int(entry.value), {"bridges": int(b.value), "components": int(c.value)}
 

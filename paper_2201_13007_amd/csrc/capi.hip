@@ -31,7 +31,10 @@ int medoid_device(const float *base, int64_t n, int d, int64_t ld, int32_t *out,
 int prune_device(const float *base, int64_t n, int d, int64_t ld, int metric, const int32_t *cand, int kc, int R,
                  int mode, int32_t *adj, hipStream_t s);
 int repair_device(const float *base, int64_t n, int d, int64_t ld, int metric, int32_t *adj_dev, int R,
-                  int32_t entry, int keep_local, int64_t *bridges_out, int64_t *ncomp_out, hipStream_t s);
+                  int32_t entry, int keep_local, int hubs, int hub_keep_local, int64_t *bridges_out,
+                  int64_t *ncomp_out, hipStream_t s);
+int reverse_edges_device(const float *base, int64_t n, int d, int64_t ld, int metric, int32_t *adj_dev, int R,
+                         int64_t *added_out, hipStream_t s);
 
 static int check_device()
 {
@@ -128,7 +131,8 @@ int sa_prune(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t me
 }
 
 int sa_repair(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, int32_t *adj_dev, int32_t R,
-              int32_t entry, int32_t keep_local, int64_t *bridges_out, int64_t *components_out, void *hip_stream)
+              int32_t entry, int32_t keep_local, int32_t hubs, int32_t hub_keep_local, int64_t *bridges_out,
+              int64_t *components_out, void *hip_stream)
 {
     int rc;
     if ((rc = check_matrix(base_dev, n, d, ld, "base")) != SA_OK) return rc;
@@ -136,15 +140,31 @@ int sa_repair(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t m
     if (R < 1 || R > 64) return set_error(SA_EINVAL, "R=%d must be in [1, 64]", R);
     if (entry < 0 || entry >= n) return set_error(SA_EINVAL, "entry %d out of range", entry);
     if (keep_local < 0 || keep_local > R) return set_error(SA_EINVAL, "keep_local must be in [0, R]");
+    if (hub_keep_local < 0 || hub_keep_local > R) return set_error(SA_EINVAL, "hub_keep_local must be in [0, R]");
+    if (hubs < 0) return set_error(SA_EINVAL, "hubs must be >= 0");
     if (!adj_dev) return set_error(SA_EINVAL, "adjacency is NULL");
     if ((rc = check_device()) != SA_OK) return rc;
-    return repair_device(base_dev, n, d, ld, metric, adj_dev, R, entry, keep_local, bridges_out, components_out,
-                         (hipStream_t)hip_stream);
+    return repair_device(base_dev, n, d, ld, metric, adj_dev, R, entry, keep_local, hubs, hub_keep_local, bridges_out,
+                         components_out, (hipStream_t)hip_stream);
+}
+
+int sa_reverse_edges(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, int32_t *adj_dev,
+                     int32_t R, int64_t *added_out, void *hip_stream)
+{
+    int rc;
+    if ((rc = check_matrix(base_dev, n, d, ld, "base")) != SA_OK) return rc;
+    if (n < 1 || n >= (int64_t(1) << 31)) return set_error(SA_EINVAL, "n must be in [1, 2^31)");
+    if (R < 1 || R > 64) return set_error(SA_EINVAL, "R=%d must be in [1, 64]", R);
+    if (metric != SA_L2 && metric != SA_IP) return set_error(SA_EINVAL, "unknown metric %d", metric);
+    if (!adj_dev) return set_error(SA_EINVAL, "adjacency is NULL");
+    if ((rc = check_device()) != SA_OK) return rc;
+    return reverse_edges_device(base_dev, n, d, ld, metric, adj_dev, R, added_out, (hipStream_t)hip_stream);
 }
 
 int sa_build_graph(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, int32_t knn_k, int32_t R,
-                   int32_t prune, int32_t repair, int32_t keep_local, int32_t *adj_dev, int32_t *entry_out,
-                   int64_t *bridges_out, int64_t *components_out, void *hip_stream)
+                   int32_t prune, int32_t repair, int32_t keep_local, int32_t hubs, int32_t hub_keep_local,
+                   int32_t *adj_dev, int32_t *entry_out, int64_t *bridges_out, int64_t *components_out,
+                   void *hip_stream)
 {
     int rc;
     if ((rc = check_matrix(base_dev, n, d, ld, "base")) != SA_OK) return rc;
@@ -152,6 +172,8 @@ int sa_build_graph(const float *base_dev, int64_t n, int32_t d, int64_t ld, int3
     if (knn_k < 1 || knn_k > 64) return set_error(SA_EINVAL, "knn_k=%d must be in [1, 64]", knn_k);
     if (R < 1 || R > 64) return set_error(SA_EINVAL, "R=%d must be in [1, 64]", R);
     if (!adj_dev || !entry_out) return set_error(SA_EINVAL, "NULL output");
+    if (keep_local < 0 || keep_local > R || hub_keep_local < 0 || hub_keep_local > R || hubs < 0)
+        return set_error(SA_EINVAL, "keep_local and hub_keep_local must be in [0, R], hubs >= 0");
     if ((rc = check_device()) != SA_OK) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     if ((rc = medoid_device(base_dev, n, d, ld, entry_out, s)) != SA_OK) return rc;
@@ -172,8 +194,10 @@ int sa_build_graph(const float *base_dev, int64_t n, int32_t d, int64_t ld, int3
     (void)hipFree(cd);
     if (bridges_out) *bridges_out = 0;
     if (components_out) *components_out = 0;
+    if (rc == SA_OK && repair) rc = reverse_edges_device(base_dev, n, d, ld, metric, adj_dev, R, nullptr, s);
     if (rc == SA_OK && repair)
-        rc = repair_device(base_dev, n, d, ld, metric, adj_dev, R, *entry_out, keep_local, bridges_out, components_out, s);
+        rc = repair_device(base_dev, n, d, ld, metric, adj_dev, R, *entry_out, keep_local, hubs, hub_keep_local,
+                           bridges_out, components_out, s);
     return rc;
 }
 

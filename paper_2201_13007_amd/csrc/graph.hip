@@ -164,6 +164,17 @@ __global__ void nearest_marked(const float *base, int64_t n, int d, int64_t ld, 
     if (threadIdx.x == 0 && sk[0] != KEY_EMPTY) atomicMin(result, sk[0]);
 }
 
+// distance of every edge p -> c, computed as d(c, p)
+__global__ void edge_dists(const float *base, int64_t n, int d, int64_t ld, int metric, const int32_t *adj, int R,
+                           float *out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * R) return;
+    const int64_t p = e / R;
+    const int32_t c = adj[e];
+    out[e] = (c >= 0 && c < n) ? dist_seq(base + (int64_t)c * ld, base + p * ld, d, metric) : 0.f;
+}
+
 __global__ void set_marks(uint8_t *mask, const int32_t *list, int64_t cnt)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -299,8 +310,66 @@ int prune_device(const float *base, int64_t n, int d, int64_t ld, int metric, co
     return SA_OK;
 }
 
+int reverse_edges_device(const float *base, int64_t n, int d, int64_t ld, int metric, int32_t *adj_dev, int R,
+                         int64_t *added_out, hipStream_t s)
+{
+    const int64_t ne = n * R;
+    DevBuf<float> dd;
+    if (dd.alloc(ne) != hipSuccess) return set_error(SA_ENOMEM, "reverse edges: device allocation failed");
+    hipLaunchKernelGGL(edge_dists, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, base, n, d, ld, metric,
+                       adj_dev, R, dd.p);
+    SA_HIP(hipGetLastError());
+    std::vector<int32_t> snap((size_t)ne);
+    std::vector<float> ed((size_t)ne);
+    SA_HIP(hipMemcpyAsync(snap.data(), adj_dev, sizeof(int32_t) * ne, hipMemcpyDeviceToHost, s));
+    SA_HIP(hipMemcpyAsync(ed.data(), dd.p, sizeof(float) * ne, hipMemcpyDeviceToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+    // in-edges grouped by target, each group in key order (d(c, p), p)
+    std::vector<int64_t> start(n + 1, 0);
+    for (int64_t e = 0; e < ne; ++e)
+        if (snap[e] >= 0 && snap[e] < n) start[snap[e] + 1]++;
+    for (int64_t c = 0; c < n; ++c) start[c + 1] += start[c];
+    struct In {
+        float d;
+        int32_t p;
+    };
+    std::vector<In> in((size_t)start[n]);
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t e = 0; e < ne; ++e) {
+            const int32_t c = snap[e];
+            if (c >= 0 && c < n) in[fill[c]++] = {ed[e], (int32_t)(e / R)};
+        }
+    }
+    std::vector<int32_t> adj(snap);
+    int64_t added = 0;
+    for (int64_t c = 0; c < n; ++c) {
+        int deg = 0;
+        while (deg < R && adj[c * R + deg] >= 0) ++deg;
+        if (deg >= R || start[c + 1] == start[c]) continue;
+        In *b = in.data() + start[c], *e = in.data() + start[c + 1];
+        std::sort(b, e, [](const In &x, const In &y) { return key_less_host(x.d, x.p, y.d, y.p); });
+        for (In *it = b; it != e && deg < R; ++it) {
+            bool dup = false;
+            for (int r = 0; r < deg; ++r)
+                if (adj[c * R + r] == it->p) {
+                    dup = true;
+                    break;
+                }
+            if (dup) continue;
+            adj[c * R + deg++] = it->p;
+            ++added;
+        }
+    }
+    SA_HIP(hipMemcpyAsync(adj_dev, adj.data(), sizeof(int32_t) * ne, hipMemcpyHostToDevice, s));
+    SA_HIP(hipStreamSynchronize(s));
+    if (added_out) *added_out = added;
+    return SA_OK;
+}
+
 int repair_device(const float *base, int64_t n, int d, int64_t ld, int metric, int32_t *adj_dev, int R,
-                  int32_t entry, int keep_local, int64_t *bridges_out, int64_t *ncomp_out, hipStream_t s)
+                  int32_t entry, int keep_local, int hubs, int hub_keep_local, int64_t *bridges_out,
+                  int64_t *ncomp_out, hipStream_t s)
 {
     std::vector<int32_t> adj((size_t)n * R);
     std::vector<float> X((size_t)n * ld);
@@ -340,55 +409,102 @@ int repair_device(const float *base, int64_t n, int d, int64_t ld, int metric, i
     for (int64_t c = 0; c < nc; ++c) rep[c] = host_medoid(X.data(), ld, d, members.data() + start[c], start[c + 1] - start[c]);
     if (ncomp_out) *ncomp_out = nc;
 
-    // (2) gateway rows
-    const int cap = R - keep_local;
-    if (nc > 1 && cap > 0) {
-        bool entry_is_rep = std::find(rep.begin(), rep.end(), entry) != rep.end();
-        const int64_t nsrc = nc + (entry_is_rep ? 0 : 1);
-        std::vector<int32_t> links((size_t)nsrc * cap, -1);
+    // (2) gateway rows for the representatives, the entry and the hubs (the vertices
+    // nearest to the mean of all rows)
+    std::vector<uint8_t> is_rep(n, 0);
+    for (int64_t c = 0; c < nc; ++c) is_rep[rep[c]] = 1;
+    std::vector<int32_t> hub;
+    if (nc > 1) {
+        if (!is_rep[entry]) hub.push_back(entry);
+        if (hubs > 1) {
+            std::vector<double> mean(d, 0.0);
+            for (int64_t v = 0; v < n; ++v)
+                for (int i = 0; i < d; ++i) mean[i] += (double)X[(size_t)v * ld + i];
+            for (int i = 0; i < d; ++i) mean[i] /= (double)n;
+            struct H {
+                double d;
+                int32_t v;
+            };
+            std::vector<H> hv;
+            hv.reserve(n);
+            for (int64_t v = 0; v < n; ++v) {
+                if (is_rep[v] || v == entry) continue;
+                double acc = 0.0;
+                for (int i = 0; i < d; ++i) {
+                    double t = (double)X[(size_t)v * ld + i] - mean[i];
+                    acc += t * t;
+                }
+                hv.push_back({acc, (int32_t)v});
+            }
+            const size_t take = std::min(hv.size(), (size_t)(hubs - 1));
+            std::partial_sort(hv.begin(), hv.begin() + take, hv.end(),
+                              [](const H &x, const H &y) { return x.d < y.d || (x.d == y.d && x.v < y.v); });
+            for (size_t j = 0; j < take; ++j) hub.push_back(hv[j].v);
+        }
+    }
+    const int64_t nsrc = nc > 1 ? nc + (int64_t)hub.size() : 0;
+    if (nsrc > 0) {
+        // representative-to-representative distances, used by the occlusion test
+        std::vector<float> rd((size_t)nc * nc);
+        for (int64_t i = 0; i < nc; ++i)
+            for (int64_t j = 0; j < nc; ++j)
+                rd[(size_t)i * nc + j] = host_dist(&X[(size_t)rep[i] * ld], &X[(size_t)rep[j] * ld], d, metric);
+        std::vector<int32_t> links((size_t)nsrc * R, -1);
+        std::vector<int> kept_local(nsrc);
         for (int64_t a = 0; a < nsrc; ++a) {
-            const int32_t v = a < nc ? rep[a] : entry;
-            struct C {
+            const int32_t v = a < nc ? rep[a] : hub[a - nc];
+            const int kl = a < nc ? keep_local : hub_keep_local;
+            kept_local[a] = kl;
+            const int cap = R - kl;
+            if (cap <= 0) continue;
+            struct Cd {
                 float d;
                 int32_t id;
+                int32_t c;
                 bool used;
             };
-            std::vector<C> cand;
+            std::vector<Cd> cand;
             cand.reserve(nc);
             for (int64_t c = 0; c < nc; ++c) {
                 if (rep[c] == v) continue;
-                cand.push_back({host_dist(&X[(int64_t)v * ld], &X[(int64_t)rep[c] * ld], d, metric), rep[c], false});
+                cand.push_back({host_dist(&X[(size_t)v * ld], &X[(size_t)rep[c] * ld], d, metric), rep[c], (int32_t)c,
+                                false});
             }
-            std::sort(cand.begin(), cand.end(), [](const C &x, const C &y) { return key_less_host(x.d, x.id, y.d, y.id); });
-            int32_t *out = &links[(size_t)a * cap];
-            int kept = 0;
+            std::sort(cand.begin(), cand.end(), [](const Cd &x, const Cd &y) { return key_less_host(x.d, x.id, y.d, y.id); });
+            int32_t *out = &links[(size_t)a * R];
+            std::vector<int32_t> kc;
             for (auto &c : cand) {
-                if (kept >= cap) break;
+                if ((int)kc.size() >= cap) break;
                 bool keep = true;
-                for (int x = 0; x < kept && keep; ++x)
-                    if (host_dist(&X[(int64_t)out[x] * ld], &X[(int64_t)c.id * ld], d, metric) < c.d) keep = false;
+                for (int32_t x : kc)
+                    if (rd[(size_t)x * nc + c.c] < c.d) {
+                        keep = false;
+                        break;
+                    }
                 if (keep) {
-                    out[kept++] = c.id;
+                    kc.push_back(c.c);
                     c.used = true;
                 }
             }
+            int kept = 0;
+            for (int32_t x : kc) out[kept++] = rep[x];
             for (auto &c : cand) {
                 if (kept >= cap) break;
                 if (!c.used) out[kept++] = c.id;
             }
         }
         for (int64_t a = 0; a < nsrc; ++a) {
-            const int32_t v = a < nc ? rep[a] : entry;
+            const int32_t v = a < nc ? rep[a] : hub[a - nc];
             int32_t *rw = &adj[(int64_t)v * R];
-            const int32_t *lk = &links[(size_t)a * cap];
+            const int32_t *lk = &links[(size_t)a * R];
             std::vector<int32_t> nr;
-            for (int r = 0; r < R && (int)nr.size() < keep_local; ++r) {
+            for (int r = 0; r < R && (int)nr.size() < kept_local[a]; ++r) {
                 const int32_t u = rw[r];
                 if (u < 0) continue;
-                if (std::find(lk, lk + cap, u) != lk + cap) continue;
+                if (std::find(lk, lk + R, u) != lk + R) continue;
                 nr.push_back(u);
             }
-            for (int x = 0; x < cap; ++x)
+            for (int x = 0; x < R; ++x)
                 if (lk[x] >= 0) nr.push_back(lk[x]);
             for (int r = 0; r < R; ++r) rw[r] = r < (int)nr.size() ? nr[r] : -1;
         }

@@ -560,7 +560,9 @@ void resolve_params(const sa_search_params &in, int L, int M, int R, int &llog2,
     else llog2 = M <= 2 ? 11 : 12;
     if (in.ws_hash_slots > 0) glog2 = ilog2_exact(in.ws_hash_slots);
     else {
-        int64_t want = 32ll * L * ((M + 3) / 4);
+        // the visited set holds at most 1 + E * R vertices after E expansions, and E stays
+        // close to L; 64 L slots keep three quarters of the table above 1.5 L * 32
+        int64_t want = 64ll * L;
         if (want < 4096) want = 4096;
         glog2 = ilog2_exact(want);
     }

@@ -75,4 +75,6 @@ def test_validation_errors_without_device(B):
     assert "aligned" in _err(B)
     assert L.sa_prune(fake, 10, 32, 32, 0, fake, 65, 16, 1, fake, None) == -1
     e = C.c_int32(0)
-    assert L.sa_build_graph(fake, 1, 32, 32, 0, 16, 16, 0, 0, 1, fake, C.byref(e), None, None, None) == -1
+    assert L.sa_build_graph(fake, 1, 32, 32, 0, 16, 16, 0, 0, 1, 4, 4, fake, C.byref(e), None, None, None) == -1
+    assert L.sa_build_graph(fake, 100, 32, 32, 0, 16, 16, 1, 1, 1, 4, 17, fake, C.byref(e), None, None, None) == -1
+    assert "hub_keep_local" in _err(B)

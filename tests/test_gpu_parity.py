@@ -103,10 +103,24 @@ def test_prune(B, mode):
     np.testing.assert_array_equal(got, want)
 
 
+def test_reverse_edges(B):
+    w = synth.sift_like(n=12_000, nq=1)
+    cand, _ = oracle.knn(w.base, w.base, 64, exclude_self=True)
+    adj0 = oracle.prune(w.base, cand, 32, "rng")
+    want = adj0.copy()
+    wa = oracle.reverse_edges(w.base, want)
+    print(f"case: reverse edges 12000x128 added={wa}", flush=True)
+    g = dev(adj0)
+    ga = B.reverse_edges(dev(w.base), g)
+    np.testing.assert_array_equal(host(g), want)
+    assert ga == wa
+
+
 def test_repair(B):
     w = synth.sift_like(n=12_000, nq=1)
     cand, _ = oracle.knn(w.base, w.base, 64, exclude_self=True)
     adj0 = oracle.prune(w.base, cand, 32, "rng")
+    oracle.reverse_edges(w.base, adj0)
     entry = oracle.medoid(w.base)
     want = adj0.copy()
     wb, wc = oracle.repair(w.base, want, entry, keep_local=1)

@@ -286,7 +286,7 @@ def test_repair_makes_everything_reachable():
     pts = np.array([[0], [1], [2], [100], [101], [102]], np.float32)
     adj = np.array([[1, -1, -1, -1], [2, -1, -1, -1], [1, -1, -1, -1],
                     [4, -1, -1, -1], [5, -1, -1, -1], [4, -1, -1, -1]], np.int32)
-    added, ncomp = oracle.repair(pts, adj, 0, keep_local=1)
+    added, ncomp = oracle.repair(pts, adj, 0, keep_local=1, hubs=1, hub_keep_local=1)
     assert ncomp == 2
     cnt, _ = oracle.reachable(adj, 0)
     assert cnt == 6
@@ -309,3 +309,38 @@ def test_generator_prefix_property():
     assert (a.base == np.rint(a.base)).all()
     c = synth.deep_like(n=500, nq=5)
     np.testing.assert_allclose(np.linalg.norm(c.base, axis=1), 1.0, rtol=1e-5)
+
+
+def test_reverse_edges_hand_case():
+    # a directed path 0 -> 1 -> 2 -> 3 -> 4 on a line, R = 2: every vertex but 0 gains
+    # its in-edge source; 4 had an empty row
+    pts = np.arange(5, dtype=np.float32)[:, None]
+    adj = np.array([[1, -1], [2, -1], [3, -1], [4, -1], [-1, -1]], np.int32)
+    assert oracle.reverse_edges(pts, adj) == 4
+    assert adj.tolist() == [[1, -1], [2, 0], [3, 1], [4, 2], [3, -1]]
+    # sources are taken nearest first, existing edges are not duplicated, full rows stay
+    pts = np.array([[0], [1], [3], [10]], np.float32)
+    adj = np.array([[1, -1], [0, -1], [0, -1], [0, 1]], np.int32)
+    assert oracle.reverse_edges(pts, adj) == 2
+    assert adj.tolist() == [[1, 2], [0, 3], [0, -1], [0, 1]]
+
+
+def test_repair_hubs_are_nearest_to_mean():
+    """Hand case.  Components {0,1,2}, {3,4}, {5,6,7} with representatives (medoids) 1,
+    3 (tie 50/51 to the smaller id) and 6.  The mean of all rows is 50.875, so after
+    the entry 4 the nearest vertex that is not a representative is 2 (3 is one).
+    Gateway rows (R = 3, one local edge kept): rep 1 -> [2 | 3, 6] (6 occluded by 3,
+    then filled); rep 3 -> [4 | 1, 6]; rep 6 -> [7 | 3, 1]; entry 4 -> [3, 6] (its edge
+    to 3 is a link; 6 kept as d(3,6)=2500 >= d(4,6)=2401; cap 2); hub 2 -> [1, 3].
+    Then vertices 0 and 5 are unreachable from 4 and get one bridge each."""
+    pts = np.array([[0], [1], [2], [50], [51], [100], [101], [102]], np.float32)
+    adj = np.array([[1, -1, -1], [2, -1, -1], [1, -1, -1], [4, -1, -1], [3, -1, -1],
+                    [6, -1, -1], [7, -1, -1], [6, -1, -1]], np.int32)
+    added, ncomp = oracle.repair(pts, adj, 4, keep_local=1, hubs=2, hub_keep_local=1)
+    assert ncomp == 3 and added == 2
+    assert adj[1].tolist() == [2, 3, 6]
+    assert adj[3].tolist() == [4, 1, 6]
+    assert adj[6].tolist() == [7, 3, 1]
+    assert adj[4].tolist() == [3, 6, -1]
+    assert adj[2].tolist()[:2] == [1, 3]
+    assert oracle.reachable(adj, 4)[0] == 8
