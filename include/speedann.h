@@ -59,8 +59,9 @@ typedef struct {
     int32_t max_substeps;   /* stop a query after this many local steps (flag in stats);
                                0 = 1<<22 */
     int32_t lds_hash_slots; /* visited-set slots kept in on-chip LDS per query, power of
-                               two >= 64; 0 = chosen from L and M.  A query whose visited set
-                               outgrows half of it moves the set to the workspace. */
+                               two >= 64; -1 = none (the set starts in the workspace);
+                               0 = chosen from M.  A query whose visited set outgrows half
+                               of it moves the set to the workspace. */
     int32_t ws_hash_slots;  /* visited-set slots per query in the workspace, power of two;
                                0 = chosen from L and M */
 } sa_search_params;
@@ -165,14 +166,17 @@ size_t sa_search_workspace_bytes(const sa_index *index, int64_t nq, int32_t k, i
 
 /* Intra-query parallel search (Algorithm 3; Algorithm 1 when M = 1), one workgroup per
  * query and one wavefront per worker:
- *   queries_dev  nq x d float32, stride ldq floats (16-byte aligned rows)
+ *   queries_dev  nq x d float32, stride ldq floats (16-byte aligned rows); d <= 1024
  *   k, L         results per query and queue capacity, 1 <= k <= L <= 1024
  *   M            workers (the paper's T, the maximum expansion width), 1 <= M <= 16
  *   params       NULL for defaults
  *   ids_dev      nq x k int32, dists_dev nq x k float32; padded with (-1, +inf) when
  *                fewer than k vertices were reached
  *   stats_dev    NULL or nq sa_query_stats
- *   workspace    sa_search_workspace_bytes(...) bytes of device memory, 256-byte aligned
+ *   workspace    sa_search_workspace_bytes(...) bytes of device memory, 256-byte aligned,
+ *                zero-filled before its first use.  Every call leaves it zero-filled again
+ *                when it completes, so one buffer serves any number of calls; calls that
+ *                share a workspace must not overlap.
  * Allocates nothing.  Enqueued on hip_stream. */
 int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64_t ldq, int32_t k, int32_t L,
               int32_t M, const sa_search_params *params, int32_t *ids_dev, float *dists_dev,

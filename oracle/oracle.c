@@ -323,7 +323,8 @@ int or_speedann(const float *base, int64_t n, int d, int64_t ld, int metric, con
                 for (int64_t j = 0; j < LSlen[t]; ++j) if (Q[j].state == ST_UNCHECKED) { any = 1; break; }
             }
             if (!any) break;
-            if (max_substeps > 0 && s.substeps >= max_substeps) { rc = 1; goto finish; }
+            /* step limit (not part of the paper): merge, then stop */
+            if (max_substeps > 0 && s.substeps >= max_substeps) { rc = 1; break; }
             s.substeps++; sub_in_step++;
             for (int t = 0; t < m; ++t) {
                 entry *Q = LS + (int64_t)t * (L + R);
@@ -385,9 +386,9 @@ int or_speedann(const float *base, int64_t n, int d, int64_t ld, int metric, con
             ++len;
         }
         s.merges++;
+        if (rc == 1) break;
         if (staged && m < T) m = (2 * m < T) ? 2 * m : T;
     }
-finish:
     emit(S, len, k, ids, dists);
     if (st) *st = s;
     free(visited); free(S); free(LS); free(LSlen); free(U); free(all);

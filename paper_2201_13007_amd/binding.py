@@ -234,8 +234,9 @@ class Index:
         return int(lib().sa_search_workspace_bytes(self._h, nq, k, L, M, C.byref(params)))
 
     def workspace(self, nbytes: int) -> torch.Tensor:
+        """Zero-filled device workspace; sa_search leaves it zero-filled."""
         if self._ws is None or self._ws.numel() < nbytes:
-            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.vec.device)
+            self._ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=self.vec.device)
         return self._ws
 
     def search(self, queries: torch.Tensor, k: int, L: int, M: int = 1, params: SearchParams | None = None,

@@ -1,0 +1,836 @@
+// Intra-query parallel graph search (Speed-ANN, arXiv 2201.13007, Algorithm 3 with
+// CheckMetrics of Algorithm 2; Algorithm 1 when there is one worker), for gfx950.
+//
+// One workgroup runs one query; worker t of Algorithm 3 is wavefront t.
+//
+// Each worker's local queue LS[t] (capacity L) lives in that wavefront's registers:
+// NI = ceil(L / 64) slots per lane hold the sorted 64-bit keys (distance bits, id) and a
+// 32-bit tag each, entry p in slot p / 64 of lane p % 64.  The tag holds the index of
+// the S entry it was copied from (0xFFFF for vertices the worker inserted itself), MINE
+// (the worker may expand it) and CHECKED.  Finding the first candidate to expand,
+// counting smaller keys and inserting (a shift by one lane) are ballots and cross-lane
+// moves: no memory round trip.
+//
+// Global steps with one active worker (every step when M = 1; the first step of a
+// staged search) run on wavefront 0 alone, with no barrier: the merge of a single local
+// queue into S leaves S equal to that queue, so S is the queue in registers.  With two
+// or more workers S sits in LDS, the local steps proceed in lockstep between two
+// barriers, and the merge ranks every surviving entry by counting smaller keys across
+// the queues.
+//
+// The visited set is an open-addressing hash of 64-bit entries ((id + 1) << 32 | tag),
+// zero meaning empty, kept in LDS or in a per-query region of the caller's workspace
+// (a query moves it there when the LDS table passes half full).  A vertex reached by
+// several workers in one local step goes to the lowest (worker, adjacency slot): claims
+// carry that order in their tag and the smallest tag of the step wins (two phases around
+// a barrier), which is the order a sequential emulation visits them in.  Workspace slots
+// a query writes are listed and zeroed again before it ends, so the workspace stays
+// zero-filled between launches.
+#pragma once
+#include "sa_internal.h"
+
+namespace sa {
+namespace search_detail {
+
+constexpr uint32_t META_SIDX = 0xFFFFu;
+constexpr uint32_t META_MINE = 1u << 16;
+constexpr uint32_t META_CHK = 1u << 17;
+constexpr int MAXW = 16;
+constexpr uint32_t NO_SLOT = 0xFFFFFFFFu;
+
+struct Ctrl {
+    int32_t lslen[MAXW];
+    int32_t U[MAXW];
+    int32_t work[MAXW];
+    int32_t nnew[MAXW];
+    int32_t slen;
+    int32_t hcount;   // visited vertices
+    int32_t nexp;     // expansions
+    int32_t mode;     // 0: visited set in LDS, 1: in the workspace
+    int32_t flags;
+    int32_t nslot;    // workspace-table slots written (zeroed again at the end)
+    int32_t done;     // the search ended while one worker was active
+    int32_t gsteps, substeps, merges, epoch;
+    int32_t pad;
+};
+
+struct KArgs {
+    const float *vec;
+    int64_t ld;
+    const int32_t *adj;
+    const float *queries;
+    int64_t ldq;
+    int32_t *ids;
+    float *dists;
+    sa_query_stats *stats;
+    unsigned long long *ghash;   // per query: 2^glog2 table entries, then 2^glog2 slot indices
+    int64_t n;
+    int32_t d, metric, R, entry, k, L, M, sync, static_I, staged, max_substeps;
+    double rho;
+    int32_t glog2, llog2;        // llog2 == 0: no LDS table
+    uint32_t o_skey, o_srank, o_schk, o_lskey, o_lsmeta, o_newkey, o_claim, o_ctrl, o_hash;
+};
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t id, int log2cap)
+{
+    return (id * 2654435761u) >> (32 - log2cap);
+}
+
+__device__ __forceinline__ uint32_t rdlane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l)
+{
+    return ((uint64_t)rdlane((uint32_t)(v >> 32), l) << 32) | rdlane((uint32_t)v, l);
+}
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, 1, 64);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), 1, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t wave_min64(uint64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        uint64_t o = (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// Phase one of a claim: find or insert u, leaving the smallest tag of this local step
+// in its slot.  Returns the slot, or NO_SLOT if the table is full; *fresh tells whether
+// this call inserted u.
+__device__ uint32_t visit_claim(unsigned long long *H, int log2cap, uint32_t u, uint32_t tag, uint32_t epoch,
+                                bool *fresh)
+{
+    const uint32_t mask = (1u << log2cap) - 1u;
+    uint32_t s = hash_slot(u, log2cap);
+    const unsigned long long want = ((unsigned long long)(u + 1) << 32) | tag;
+    *fresh = false;
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        unsigned long long old = atomicCAS(&H[s], 0ull, want);
+        if (old == 0ull) {
+            *fresh = true;
+            return s;
+        }
+        if ((uint32_t)(old >> 32) == u + 1) {
+            if (((uint32_t)old >> 10) == epoch) atomicMin(&H[s], want);
+            return s;
+        }
+        s = (s + 1) & mask;
+    }
+    return NO_SLOT;
+}
+
+__device__ __forceinline__ unsigned long long read_slot_global(unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// lower_bound: number of entries of the sorted array a[0..n) smaller than key
+__device__ __forceinline__ int lower_bound(const uint64_t *a, int n, uint64_t key)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- register queue
+
+template <int NI>
+struct RList {
+    uint64_t k[NI];
+    uint32_t m[NI];
+};
+
+template <int NI>
+__device__ __forceinline__ void rl_clear(RList<NI> &l)
+{
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        l.k[i] = KEY_EMPTY;
+        l.m[i] = 0;
+    }
+}
+
+// entries with a key smaller than key (unused slots hold KEY_EMPTY)
+template <int NI>
+__device__ __forceinline__ int rl_count_less(const RList<NI> &l, uint64_t key)
+{
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) c += __popcll(__ballot(l.k[i] < key));
+    return c;
+}
+
+// first entry the worker may expand (MINE and not CHECKED), or NI * 64
+template <int NI>
+__device__ __forceinline__ int rl_first_expandable(const RList<NI> &l)
+{
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const uint64_t b = __ballot((l.m[i] & (META_MINE | META_CHK)) == META_MINE);
+        if (b) return i * 64 + __builtin_ctzll(b);
+    }
+    return NI * 64;
+}
+
+template <int NI>
+__device__ __forceinline__ void rl_get(const RList<NI> &l, int p, uint64_t &key, uint32_t &meta)
+{
+    const int i = p >> 6, ln = p & 63;
+    key = KEY_EMPTY;
+    meta = 0;
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii)
+        if (ii == i) {
+            key = rdlane64(l.k[ii], ln);
+            meta = rdlane(l.m[ii], ln);
+        }
+}
+
+template <int NI>
+__device__ __forceinline__ void rl_or_meta(RList<NI> &l, int p, uint32_t bits)
+{
+    const int i = p >> 6, ln = p & 63;
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii)
+        if (ii == i && __lane_id() == ln) l.m[ii] |= bits;
+}
+
+// insert one entry, keeping the queue sorted and at most L long
+template <int NI>
+__device__ __forceinline__ void rl_insert(RList<NI> &l, int L, uint64_t key, uint32_t meta)
+{
+    const int pos = rl_count_less(l, key);
+    if (pos >= L) return;
+    const int lane = __lane_id();
+    uint64_t ck = KEY_EMPTY;
+    uint32_t cm = 0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        if ((i + 1) * 64 <= pos) continue;   // slot entirely before the insertion point
+        const int p = i * 64 + lane;
+        uint64_t pk = shfl_up64(l.k[i]);
+        uint32_t pm = (uint32_t)__shfl_up((int)l.m[i], 1, 64);
+        const uint64_t topk = rdlane64(l.k[i], 63);
+        const uint32_t topm = rdlane(l.m[i], 63);
+        if (lane == 0) {
+            pk = ck;
+            pm = cm;
+        }
+        uint64_t nk = p > pos ? pk : (p == pos ? key : l.k[i]);
+        uint32_t nm = p > pos ? pm : (p == pos ? meta : l.m[i]);
+        if (p >= L) {
+            nk = KEY_EMPTY;
+            nm = 0;
+        }
+        l.k[i] = nk;
+        l.m[i] = nm;
+        ck = topk;
+        cm = topm;
+    }
+}
+
+// Distances from the query (q chunks in registers) to the vectors listed in ids[0..n),
+// written as keys to out[0..n).  LPV lanes share one vector (float4 chunks c = g,
+// g + LPV, ...); every lane accumulates its chunks in double precision, the group sums
+// its lanes with a butterfly and the group's first lane rounds the sum once to float.
+template <int LPV, int CPL>
+__device__ void wave_distances(const KArgs &A, const float4 (&q)[CPL], const int32_t *ids, int n, uint64_t *out)
+{
+    constexpr int VPW = 64 / LPV;
+    constexpr int PB = CPL >= 4 ? 1 : 4 / CPL;
+    const int lane = __lane_id();
+    const int grp = lane / LPV, g = lane % LPV;
+    const int nch = A.d >> 2;
+    const int npass = (n + VPW - 1) / VPW;
+    for (int p0 = 0; p0 < npass; p0 += PB) {
+        float4 xv[PB][CPL];
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp) {
+            int idx = (p0 + pp) * VPW + grp;
+            if (idx < n) {
+                const float *row = A.vec + (int64_t)ids[idx] * A.ld;
+#pragma unroll
+                for (int i = 0; i < CPL; ++i) {
+                    int c = g + LPV * i;
+                    if (c < nch) xv[pp][i] = *reinterpret_cast<const float4 *>(row + 4 * c);
+                }
+            }
+        }
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp) {
+            int idx = (p0 + pp) * VPW + grp;
+            double acc = 0.0;
+            if (idx < n) {
+#pragma unroll
+                for (int i = 0; i < CPL; ++i) {
+                    int c = g + LPV * i;
+                    if (c < nch) {
+                        const float4 a = q[i], b = xv[pp][i];
+                        if (A.metric == SA_L2) {
+                            double t0 = (double)a.x - (double)b.x, t1 = (double)a.y - (double)b.y;
+                            double t2 = (double)a.z - (double)b.z, t3 = (double)a.w - (double)b.w;
+                            acc += t0 * t0; acc += t1 * t1; acc += t2 * t2; acc += t3 * t3;
+                        } else {
+                            acc += (double)a.x * (double)b.x; acc += (double)a.y * (double)b.y;
+                            acc += (double)a.z * (double)b.z; acc += (double)a.w * (double)b.w;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int off = LPV / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (g == 0 && idx < n) {
+                float dist = A.metric == SA_L2 ? (float)acc : (float)(-acc);
+                out[idx] = make_key(dist, ids[idx]);
+            }
+        }
+    }
+}
+
+// Records workspace slots written by fresh claims of this wave (prefix over the wave,
+// then one reservation) so they can be zeroed at the end of the query.
+__device__ __forceinline__ void record_slots(bool rec, uint32_t slot, int32_t *base_counter, uint32_t *slots)
+{
+    const uint64_t b = __ballot(rec);
+    if (!b) return;
+    int base = 0;
+    if (__lane_id() == 0) base = atomicAdd(base_counter, __popcll(b));
+    base = __shfl(base, 0, 64);
+    if (rec) slots[base + __popcll(b & lanemask_lt())] = slot;
+}
+
+// Moves the LDS visited table into the (zero-filled) workspace table.
+__device__ void migrate_table(const unsigned long long *lh, int llog2, unsigned long long *gh, int glog2,
+                              uint32_t *gslots, int32_t *nslot, int tid, int nthr)
+{
+    const uint32_t gm = (1u << glog2) - 1u;
+    for (int base = 0; base < (1 << llog2); base += nthr) {
+        const int i = base + tid;
+        bool rec = false;
+        uint32_t s = 0;
+        if (i < (1 << llog2)) {
+            const unsigned long long h = lh[i];
+            if (h != 0ull) {
+                s = hash_slot((uint32_t)(h >> 32) - 1u, glog2);
+                while (atomicCAS(&gh[s], 0ull, h) != 0ull) s = (s + 1) & gm;
+                rec = true;
+            }
+        }
+        record_slots(rec, s, nslot, gslots);
+    }
+}
+
+template <int LPV, int CPL, int NI, bool MULTI>
+__device__ __forceinline__ void search_body(const KArgs &A)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6, nthr = blockDim.x;
+    const int64_t qi = blockIdx.x;
+    const int L = A.L, M = A.M, R = A.R;
+
+    uint64_t *const skey_base = reinterpret_cast<uint64_t *>(smem + A.o_skey);
+    int32_t *const srank = reinterpret_cast<int32_t *>(smem + A.o_srank);
+    uint8_t *const schk_base = smem + A.o_schk;
+    uint64_t *const lskey_all = reinterpret_cast<uint64_t *>(smem + A.o_lskey);
+    uint64_t *const lskey = lskey_all + (size_t)w * L;
+    uint32_t *const lsmeta = reinterpret_cast<uint32_t *>(smem + A.o_lsmeta) + (size_t)w * L;
+    uint64_t *const nkey = reinterpret_cast<uint64_t *>(smem + A.o_newkey) + w * 64;
+    int32_t *const claim = reinterpret_cast<int32_t *>(smem + A.o_claim) + w * 64;
+    Ctrl *const C = reinterpret_cast<Ctrl *>(smem + A.o_ctrl);
+    unsigned long long *const lh = reinterpret_cast<unsigned long long *>(smem + A.o_hash);
+    unsigned long long *const gh = A.ghash ? A.ghash + ((size_t)qi << (A.glog2 + 1)) : nullptr;
+    uint32_t *const gslots = gh ? reinterpret_cast<uint32_t *>(gh + (1ull << A.glog2)) : nullptr;
+
+    const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+    const int max_sub = A.max_substeps;
+    const int llog2 = A.llog2, glog2 = A.glog2;
+
+    if (llog2 > 0)
+        for (int i = tid; i < (1 << llog2); i += nthr) lh[i] = 0ull;
+    if (tid == 0) {
+        C->hcount = 1;
+        C->nexp = 0;
+        C->mode = llog2 > 0 ? 0 : 1;
+        C->flags = 0;
+        C->slen = 0;
+        C->nslot = 0;
+        C->done = 0;
+        C->gsteps = C->substeps = C->merges = 0;
+        C->epoch = 1;
+    }
+    float4 q[CPL];
+    {
+        const float *qrow = A.queries + qi * A.ldq;
+        const int g = lane % LPV, nch = A.d >> 2;
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+            int c = g + LPV * i;
+            q[i] = c < nch ? *reinterpret_cast<const float4 *>(qrow + 4 * c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+    __syncthreads();
+
+    RList<NI> ls;
+    rl_clear(ls);
+    int len = 0;
+    int m = A.staged ? 1 : M;
+    int32_t pv = -1, pu = -1;   // vertex whose adjacency row is prefetched, and this lane's entry of it
+
+    // compute dist(P, Q), add P to S and mark it visited
+    if (w == 0) {
+        if (lane == 0) claim[0] = A.entry;
+        __builtin_amdgcn_wave_barrier();
+        wave_distances<LPV, CPL>(A, q, claim, 1, nkey);
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t k0 = nkey[0];
+        bool fresh = false;
+        uint32_t s0 = 0;
+        if (lane == 0) {
+            s0 = llog2 > 0 ? visit_claim(lh, llog2, (uint32_t)A.entry, 0u, 0u, &fresh)
+                           : visit_claim(gh, glog2, (uint32_t)A.entry, 0u, 0u, &fresh);
+        }
+        if (llog2 == 0) record_slots(lane == 0, s0, &C->nslot, gslots);
+        if (lane == 0) {
+            ls.k[0] = k0;
+            ls.m[0] = META_SIDX | META_MINE;
+        }
+        len = 1;
+        if (m > 1 && lane == 0) {
+            skey_base[0] = k0;
+            schk_base[0] = 0;
+            C->slen = 1;
+        }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ one active worker
+    if (m == 1) {
+        if (w == 0) {
+            int substeps = 0, gsteps = 0, merges = 0, nexp = 0, hcount = 1;
+            uint32_t epoch = 1;
+            int mode = llog2 > 0 ? 0 : 1;
+            bool done = false, stop = false;
+            int cur = rl_first_expandable(ls);
+            for (;;) {
+                // S is this queue; all its unchecked entries belong to the one worker
+                if (cur >= len) {
+                    done = true;
+                    break;
+                }
+                gsteps++;
+                int sub_in_step = 0;
+                for (;;) {
+                    if (substeps >= max_sub) {
+                        if (lane == 0) C->flags |= SA_QFLAG_MAX_STEPS;
+                        stop = true;
+                        break;
+                    }
+                    substeps++;
+                    sub_in_step++;
+                    uint64_t vkey;
+                    uint32_t vmeta;
+                    rl_get(ls, cur, vkey, vmeta);
+                    rl_or_meta(ls, cur, META_CHK);
+                    nexp++;
+                    const int32_t v = key_id(vkey);
+                    int32_t u;
+                    if (v == pv) u = pu;
+                    else u = lane < R ? A.adj[(int64_t)v * R + lane] : -1;
+                    // prefetch the row of the next candidate while this step runs
+                    const int nxt = rl_first_expandable(ls);
+                    pv = -1;
+                    if (nxt < len) {
+                        uint64_t nk;
+                        uint32_t nm;
+                        rl_get(ls, nxt, nk, nm);
+                        pv = key_id(nk);
+                        pu = lane < R ? A.adj[(int64_t)pv * R + lane] : -1;
+                    }
+                    if (u >= A.n) u = -1;   // malformed row entries are ignored like padding
+                    bool fresh = false;
+                    uint32_t slot = NO_SLOT;
+                    const uint32_t tag = (epoch << 10) | (uint32_t)lane;
+                    if (u >= 0) slot = mode ? visit_claim(gh, glog2, (uint32_t)u, tag, epoch, &fresh)
+                                            : visit_claim(lh, llog2, (uint32_t)u, tag, epoch, &fresh);
+                    if (mode) record_slots(fresh, slot, &C->nslot, gslots);
+                    const uint64_t cm = __ballot(fresh);
+                    const int nclaim = __popcll(cm);
+                    hcount += nclaim;
+                    if (fresh) claim[__popcll(cm & lanemask_lt())] = u;
+                    __builtin_amdgcn_wave_barrier();
+                    wave_distances<LPV, CPL>(A, q, claim, nclaim, nkey);
+                    __builtin_amdgcn_wave_barrier();
+                    const uint64_t mk = lane < nclaim ? nkey[lane] : KEY_EMPTY;
+                    __builtin_amdgcn_wave_barrier();
+                    // insert the new entries; the update position is where the best lands
+                    uint64_t worst = KEY_EMPTY;
+                    if (len == L) {
+                        uint32_t wm;
+                        rl_get(ls, L - 1, worst, wm);
+                    }
+                    const bool surv = lane < nclaim && mk < worst;
+                    uint64_t sbits = __ballot(surv);
+                    int U = L;
+                    if (sbits) {
+                        U = rl_count_less(ls, wave_min64(surv ? mk : KEY_EMPTY));
+                        while (sbits) {
+                            const int j = __builtin_ctzll(sbits);
+                            sbits &= sbits - 1;
+                            rl_insert(ls, L, rdlane64(mk, j), META_SIDX | META_MINE);
+                            len = min(L, len + 1);
+                        }
+                    }
+                    cur = rl_first_expandable(ls);
+                    epoch++;
+                    // keep the visited set below half (LDS) / three quarters (workspace)
+                    const int need = hcount + R;
+                    if (mode == 0 && need > (1 << llog2) / 2) {
+                        if (gh == nullptr || need > (3 << glog2) / 4) {
+                            if (lane == 0) C->flags |= SA_QFLAG_CAPACITY;
+                            stop = true;
+                            break;
+                        }
+                        migrate_table(lh, llog2, gh, glog2, gslots, &C->nslot, lane, 64);
+                        mode = 1;
+                        if (lane == 0) C->flags |= SA_QFLAG_SPILLED;
+                    } else if (mode == 1 && need > (3 << glog2) / 4) {
+                        if (lane == 0) C->flags |= SA_QFLAG_CAPACITY;
+                        stop = true;
+                        break;
+                    }
+                    bool merge_now;
+                    if (A.sync == SA_SYNC_BSP) merge_now = true;
+                    else if (A.sync == SA_SYNC_STATIC) merge_now = A.static_I > 0 && sub_in_step >= A.static_I;
+                    else merge_now = (double)U >= (double)L * A.rho;
+                    if (cur >= len || merge_now) break;
+                }
+                merges++;   // S becomes this queue unchanged
+                if (stop) break;
+                if (M > 1) {
+                    m = 2;
+                    break;
+                }
+            }
+            if (!done && !stop) {
+                // hand S to the workers through LDS
+#pragma unroll
+                for (int i = 0; i < NI; ++i) {
+                    const int p = i * 64 + lane;
+                    if (p < len) {
+                        skey_base[p] = ls.k[i];
+                        schk_base[p] = (ls.m[i] & META_CHK) ? 1 : 0;
+                    }
+                }
+            }
+            if (lane == 0) {
+                C->done = (done || stop) ? 1 : 0;
+                C->slen = len;
+                C->hcount = hcount;
+                C->nexp = nexp;
+                C->mode = mode;
+                C->gsteps = gsteps;
+                C->substeps = substeps;
+                C->merges = merges;
+                C->epoch = (int)epoch;
+            }
+        }
+        __syncthreads();
+        m = 2;
+    }
+
+    // ------------------------------------------------------------ two or more workers
+    int sb = 0;
+    if (MULTI && !C->done) {
+        int substeps = C->substeps, gsteps = C->gsteps, merges = C->merges;
+        uint32_t epoch = (uint32_t)C->epoch;
+        pv = -1;
+        for (;;) {
+            uint64_t *S = skey_base + sb * L;
+            uint8_t *Sc = schk_base + sb * L;
+            const int slen = C->slen;
+            // divide the unchecked entries of S among the m workers: the j-th unchecked
+            // entry belongs to worker j mod m; every local queue starts as a copy of S
+            int running = 0;
+            rl_clear(ls);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const int j = i * 64 + lane;
+                const bool valid = j < slen;
+                const uint8_t chk = valid ? Sc[j] : 1;
+                const bool unc = valid && !chk;
+                const uint64_t msk = __ballot(unc);
+                const int r = running + __popcll(msk & lanemask_lt());
+                running += __popcll(msk);
+                if (w < m && valid) {
+                    ls.k[i] = S[j];
+                    ls.m[i] = (uint32_t)j | (chk ? META_CHK : 0u) | ((unc && (r % m) == w) ? META_MINE : 0u);
+                }
+            }
+            for (int j = tid; j < slen; j += nthr) srank[j] = j + m * L;
+            if (running == 0) break;   // every local queue is empty of unchecked work
+            gsteps++;
+            len = (w < m) ? slen : 0;
+            int cur = (w < m) ? rl_first_expandable(ls) : NI * 64;
+            __syncthreads();
+
+            int sub_in_step = 0;
+            bool stop = false;
+            for (;;) {
+                if (substeps >= max_sub) {
+                    if (tid == 0) C->flags |= SA_QFLAG_MAX_STEPS;
+                    stop = true;
+                    break;
+                }
+                substeps++;
+                sub_in_step++;
+                const int mode = C->mode;
+                const bool has = (w < m) && (cur < len);
+                const uint32_t tag = (epoch << 10) | ((uint32_t)w << 6) | (uint32_t)lane;
+                int32_t u = -1;
+                uint32_t slot = NO_SLOT;
+                bool fresh = false;
+                if (has) {
+                    // expand the first unchecked candidate of the local queue
+                    uint64_t vkey;
+                    uint32_t vmeta;
+                    rl_get(ls, cur, vkey, vmeta);
+                    rl_or_meta(ls, cur, META_CHK);
+                    const uint32_t sidx = vmeta & META_SIDX;
+                    if (lane == 0) {
+                        if (sidx != META_SIDX) Sc[sidx] = 1;
+                        atomicAdd(&C->nexp, 1);
+                    }
+                    const int32_t v = key_id(vkey);
+                    if (v == pv) u = pu;
+                    else u = lane < R ? A.adj[(int64_t)v * R + lane] : -1;
+                    const int nxt = rl_first_expandable(ls);
+                    pv = -1;
+                    if (nxt < len) {
+                        uint64_t nk;
+                        uint32_t nm;
+                        rl_get(ls, nxt, nk, nm);
+                        pv = key_id(nk);
+                        pu = lane < R ? A.adj[(int64_t)pv * R + lane] : -1;
+                    }
+                    if (u >= A.n) u = -1;
+                    if (u >= 0) slot = mode ? visit_claim(gh, glog2, (uint32_t)u, tag, epoch, &fresh)
+                                            : visit_claim(lh, llog2, (uint32_t)u, tag, epoch, &fresh);
+                }
+                __syncthreads();
+                int U = L;
+                if (has) {
+                    bool claimed = false;
+                    if (slot != NO_SLOT) {
+                        unsigned long long h = mode ? read_slot_global(gh + slot) : lh[slot];
+                        claimed = (uint32_t)h == tag;
+                    }
+                    // the visited count changes only between the two barriers of a local
+                    // step, so every wave reads the same value in the decision below
+                    const int nfresh = __popcll(__ballot(fresh));
+                    if (lane == 0 && nfresh) atomicAdd(&C->hcount, nfresh);
+                    if (mode) record_slots(fresh, slot, &C->nslot, gslots);
+                    const uint64_t cm = __ballot(claimed);
+                    const int nclaim = __popcll(cm);
+                    if (claimed) claim[__popcll(cm & lanemask_lt())] = u;
+                    __builtin_amdgcn_wave_barrier();
+                    wave_distances<LPV, CPL>(A, q, claim, nclaim, nkey);
+                    __builtin_amdgcn_wave_barrier();
+                    const uint64_t mk = lane < nclaim ? nkey[lane] : KEY_EMPTY;
+                    __builtin_amdgcn_wave_barrier();
+                    uint64_t worst = KEY_EMPTY;
+                    if (len == L) {
+                        uint32_t wm;
+                        rl_get(ls, L - 1, worst, wm);
+                    }
+                    const bool surv = lane < nclaim && mk < worst;
+                    uint64_t sbits = __ballot(surv);
+                    if (sbits) {
+                        U = rl_count_less(ls, wave_min64(surv ? mk : KEY_EMPTY));
+                        while (sbits) {
+                            const int j = __builtin_ctzll(sbits);
+                            sbits &= sbits - 1;
+                            rl_insert(ls, L, rdlane64(mk, j), META_SIDX | META_MINE);
+                            len = min(L, len + 1);
+                        }
+                    }
+                    cur = rl_first_expandable(ls);
+                }
+                if (lane == 0 && w < m) {
+                    C->U[w] = U;
+                    C->work[w] = cur < len;
+                    C->lslen[w] = len;
+                }
+                epoch++;
+                __syncthreads();
+                bool any = false;
+                int64_t sumU = 0;
+                for (int t = 0; t < m; ++t) {
+                    any = any || C->work[t] != 0;
+                    sumU += C->U[t];
+                }
+                bool merge_now;
+                if (A.sync == SA_SYNC_BSP) merge_now = true;
+                else if (A.sync == SA_SYNC_STATIC) merge_now = A.static_I > 0 && sub_in_step >= A.static_I;
+                else merge_now = (double)sumU / (double)m >= (double)L * A.rho;
+                // keep the visited set below half (LDS) / three quarters (workspace) before
+                // the next local step, which adds at most m * R entries
+                const int need = C->hcount + m * R;
+                if (mode == 0 && need > (1 << llog2) / 2) {
+                    if (gh == nullptr || need > (3 << glog2) / 4) {
+                        if (tid == 0) C->flags |= SA_QFLAG_CAPACITY;
+                        stop = true;
+                        break;
+                    }
+                    migrate_table(lh, llog2, gh, glog2, gslots, &C->nslot, tid, nthr);
+                    __syncthreads();
+                    if (tid == 0) {
+                        C->mode = 1;
+                        C->flags |= SA_QFLAG_SPILLED;
+                    }
+                    __syncthreads();
+                } else if (mode == 1 && need > (3 << glog2) / 4) {
+                    if (tid == 0) C->flags |= SA_QFLAG_CAPACITY;
+                    stop = true;
+                    break;
+                }
+                if (!any || merge_now) break;
+            }
+
+            // merge: S' = top-L of S and every worker's surviving new entries.  An S
+            // entry's rank is its index plus, per worker, the new entries ahead of it in
+            // that worker's queue (L if the worker truncated it away); a new entry's rank
+            // is its position in its own queue plus the new entries of the other workers
+            // below it.
+            if (w < m) {
+#pragma unroll
+                for (int i = 0; i < NI; ++i) {
+                    const int p = i * 64 + lane;
+                    if (p < len) {
+                        lskey[p] = ls.k[i];
+                        lsmeta[p] = ls.m[i];
+                    }
+                }
+            }
+            __syncthreads();
+            uint64_t *Sn = skey_base + (sb ^ 1) * L;
+            uint8_t *Snc = schk_base + (sb ^ 1) * L;
+            if (w < m) {
+                int nbefore = 0;
+#pragma unroll
+                for (int i = 0; i < NI; ++i) {
+                    const int p = i * 64 + lane;
+                    const bool valid = p < len;
+                    const uint32_t meta = valid ? ls.m[i] : 0u;
+                    const uint32_t sidx = meta & META_SIDX;
+                    const bool isS = valid && sidx != META_SIDX;
+                    const bool isN = valid && sidx == META_SIDX;
+                    if (isS) atomicAdd(&srank[sidx], p - (int)sidx - L);
+                    const uint64_t nm = __ballot(isN);
+                    if (isN) {
+                        const int nidx = nbefore + __popcll(nm & lanemask_lt());
+                        const uint64_t key = ls.k[i];
+                        const int cS = p - nidx;
+                        int rank = p;
+                        for (int t = 0; t < m && rank < L; ++t) {
+                            if (t == w) continue;
+                            rank += lower_bound(lskey_all + (size_t)t * L, C->lslen[t], key) - cS;
+                        }
+                        if (rank < L) {
+                            Sn[rank] = key;
+                            Snc[rank] = (meta & META_CHK) ? 1 : 0;
+                        }
+                    }
+                    nbefore += __popcll(nm);
+                }
+                if (lane == 0) C->nnew[w] = nbefore;
+            }
+            __syncthreads();
+            for (int j = tid; j < slen; j += nthr) {
+                const int r = srank[j];
+                if (r < L) {
+                    Sn[r] = S[j];
+                    Snc[r] = Sc[j];
+                }
+            }
+            int total = slen;
+            for (int t = 0; t < m; ++t) total += C->nnew[t];
+            __syncthreads();
+            if (tid == 0) C->slen = min(L, total);
+            sb ^= 1;
+            merges++;
+            if (A.staged && m < M) m = min(2 * m, M);
+            __syncthreads();
+            if (stop) break;   // a step limit or a full visited table ends the search after this merge
+        }
+        if (tid == 0) {
+            C->gsteps = gsteps;
+            C->substeps = substeps;
+            C->merges = merges;
+        }
+    }
+
+    __syncthreads();
+    {
+        const bool from_regs = C->done != 0;   // the search ended in wavefront 0's queue
+        const int slen = C->slen;
+        if (from_regs) {
+            if (w == 0) {
+#pragma unroll
+                for (int i = 0; i < NI; ++i) {
+                    const int p = i * 64 + lane;
+                    if (p < A.k) {
+                        const bool ok = p < slen;
+                        A.ids[qi * A.k + p] = ok ? key_id(ls.k[i]) : -1;
+                        A.dists[qi * A.k + p] = ok ? key_dist(ls.k[i]) : __builtin_inff();
+                    }
+                }
+            }
+        } else {
+            const uint64_t *S = skey_base + sb * L;
+            for (int i = tid; i < A.k; i += nthr) {
+                if (i < slen) {
+                    A.ids[qi * A.k + i] = key_id(S[i]);
+                    A.dists[qi * A.k + i] = key_dist(S[i]);
+                } else {
+                    A.ids[qi * A.k + i] = -1;
+                    A.dists[qi * A.k + i] = __builtin_inff();
+                }
+            }
+        }
+        // leave the workspace table zero-filled for the next launch
+        const int ns = C->nslot;
+        for (int i = tid; i < ns; i += nthr) {
+            const uint32_t sl = gslots[i];
+            gh[sl] = 0ull;
+            gslots[i] = 0u;
+        }
+        if (tid == 0 && A.stats) {
+            sa_query_stats st;
+            st.global_steps = C->gsteps;
+            st.substeps = C->substeps;
+            st.expansions = C->nexp;
+            st.dist_comps = C->hcount;
+            st.merges = C->merges;
+            st.flags = C->flags;
+            st.t_start = t_start;
+            st.t_end = __builtin_amdgcn_s_memrealtime();
+            A.stats[qi] = st;
+        }
+    }
+}
+
+}  // namespace search_detail
+
+int launch_search_single(const search_detail::KArgs &A, int64_t nq, uint32_t lds, hipStream_t s);
+int launch_search_multi(const search_detail::KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s);
+
+}  // namespace sa

@@ -274,3 +274,19 @@ def test_search_ip_deep_shaped(B):
         print(f"case: search deep-8k ip M={M}", flush=True)
         g, e = run_both(B, w.base, adj, entry, w.queries, 10, 64, M, metric="ip", rho=0.9)
         assert_search_equal(g, e, exact=False, label=f"ip M={M}")
+
+
+def test_workspace_stays_zero_and_reusable(B, sift_setup):
+    """The visited tables in the workspace are zeroed by each query before it ends, so
+    one buffer serves calls with different table sizes back to back."""
+    w, adj, entry = sift_setup
+    ix = B.Index(dev(w.base), dev(adj), entry)
+    q = dev(w.queries)
+    for L, M, lds in ((256, 1, -1), (64, 1, -1), (128, 4, 0), (384, 2, -1), (100, 8, 1024)):
+        print(f"case: workspace reuse L={L} M={M} lds={lds}", flush=True)
+        r = ix.search(q, 10, L, M, stats=True, lds_hash_slots=lds)
+        torch.cuda.synchronize()
+        assert int(ix._ws.count_nonzero().item()) == 0, f"workspace dirty after L={L} M={M}"
+        eids, ed, est = oracle.speedann(w.base, adj, entry, w.queries, 10, L, M)
+        np.testing.assert_array_equal(host(r.ids), eids)
+        np.testing.assert_array_equal(host(r.stats)[:, 3], est["dist_comps"])
