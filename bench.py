@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--M", type=int, default=0, help="time this walker count only (0: sweep)")
     ap.add_argument("--L", type=int, default=0, help="with --M, time this L (0: sweep)")
     ap.add_argument("--sweep-json", default="")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after timing, run a plain elementwise copy of this many MiB (read and written "
+                         "once) so that a profiler run can scale its byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -186,6 +189,15 @@ def main():
     # in-batch service time of each query (device real-time counter, 100 MHz)
     t = stats.view(np.int64)[:, 3:5]
     svc_ms = (t[:, 1] - t[:, 0]) / 1e5
+    if args.copy_calibration_mib > 0:
+        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy calibration: 3 x {args.copy_calibration_mib} MiB read + written")
+
     # ---------------------------------------------------------------- batch-1 latency
     Mlat = max(s["M"] for s in sweep if s["recall"] >= TARGET) if reached else M
     Llat = min([s["L"] for s in sweep if s["M"] == Mlat and s["recall"] >= TARGET] or [L])
@@ -202,7 +214,7 @@ def main():
         run(Mlat, Llat, q=q1, out=one[0])
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - s0) * 1e3)
-    lat = np.array(lat)
+    lat = np.array(lat) if lat else np.array([float("nan")])
     log(f"batch-1 latency M={Mlat} L={Llat}: p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
 
     # ---------------------------------------------------------------- roofline
