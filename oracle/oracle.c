@@ -112,8 +112,26 @@ static const float *row(const float *base, int64_t i, int64_t ld) { return base 
 /* For each query, the k smallest keys (distance, id) over all n base vectors.
  * With exclude_self, query i (a base vector itself) skips base id i.
  * Short results are padded with (-1, +inf). */
+static void knn_impl(const float *base, int64_t n, int d, int64_t ld, const float *queries, int64_t nq,
+                     int64_t ldq, int k, int metric, int exclude_self, const int32_t *self_ids, int32_t *ids,
+                     float *dists);
+
 void or_knn(const float *base, int64_t n, int d, int64_t ld, const float *queries, int64_t nq,
             int64_t ldq, int k, int metric, int exclude_self, int32_t *ids, float *dists)
+{
+    knn_impl(base, n, d, ld, queries, nq, ldq, k, metric, exclude_self, NULL, ids, dists);
+}
+
+/* As or_knn, but query qi skips base id self_ids[qi] (queries that are base rows). */
+void or_knn_self(const float *base, int64_t n, int d, int64_t ld, const float *queries, int64_t nq,
+                 int64_t ldq, int k, int metric, const int32_t *self_ids, int32_t *ids, float *dists)
+{
+    knn_impl(base, n, d, ld, queries, nq, ldq, k, metric, 1, self_ids, ids, dists);
+}
+
+static void knn_impl(const float *base, int64_t n, int d, int64_t ld, const float *queries, int64_t nq,
+                     int64_t ldq, int k, int metric, int exclude_self, const int32_t *self_ids, int32_t *ids,
+                     float *dists)
 {
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t qi = 0; qi < nq; ++qi) {
@@ -121,7 +139,7 @@ void or_knn(const float *base, int64_t n, int d, int64_t ld, const float *querie
         int cnt = 0;
         const float *q = row(queries, qi, ldq);
         for (int64_t i = 0; i < n; ++i) {
-            if (exclude_self && i == qi) continue;
+            if (exclude_self && i == (self_ids ? (int64_t)self_ids[qi] : qi)) continue;
             float dd = or_distance(q, row(base, i, ld), d, metric);
             if (cnt == k && !key_less(dd, (int32_t)i, top[k - 1].dist, top[k - 1].id)) continue;
             /* insertion into the sorted top list */

@@ -58,6 +58,8 @@ def lib():
         L.or_distance.restype = C.c_float
         L.or_knn.argtypes = [f32p, i64, C.c_int, i64, f32p, i64, i64, C.c_int, C.c_int, C.c_int, i32p, f32p]
         L.or_knn.restype = None
+        L.or_knn_self.argtypes = [f32p, i64, C.c_int, i64, f32p, i64, i64, C.c_int, C.c_int, i32p, i32p, f32p]
+        L.or_knn_self.restype = None
         L.or_search_batch.argtypes = [C.c_int, f32p, i64, C.c_int, i64, C.c_int, i32p, C.c_int, i32, f32p, i64,
                                       i64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dbl, C.c_int, C.c_int,
                                       i32p, f32p, st]
@@ -100,6 +102,18 @@ def knn(base, queries, k, metric="l2", exclude_self=False):
     ids = np.empty((nq, k), np.int32)
     dists = np.empty((nq, k), np.float32)
     lib().or_knn(base, n, d, d, queries, nq, d, k, _metric(metric), int(exclude_self), ids, dists)
+    return ids, dists
+
+
+def knn_self(base, rows, k, metric="l2"):
+    """Exact top-k of the listed base rows, each excluding itself."""
+    base = _f32(base)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    n, d = base.shape
+    q = np.ascontiguousarray(base[rows])
+    ids = np.empty((rows.shape[0], k), np.int32)
+    dists = np.empty((rows.shape[0], k), np.float32)
+    lib().or_knn_self(base, n, d, d, q, rows.shape[0], d, k, _metric(metric), rows, ids, dists)
     return ids, dists
 
 

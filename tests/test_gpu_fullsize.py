@@ -1,0 +1,83 @@
+"""Full-size checks on the SIFT-shaped 1M x 128 workload, in the configuration bench.py
+times (graph built on the GPU, M = 1 and M = 2 at L = 384, adaptive rho 0.8, staged).
+
+The oracle cannot build a 1M graph or search it for every query in test time, so this
+checks sampled outputs the oracle computes one by one, and properties that hold at any
+size.  Data are integer-valued, so every distance is exact and compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_13007_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_2201_13007_amd import binding as B
+    B.lib()
+    w = synth.sift_like()
+    base = torch.from_numpy(w.base).cuda()
+    print("case: full-size graph build 1M x 128", flush=True)
+    adj, entry, info = B.build_graph(base, w.graph_knn, w.graph_R, w.graph_prune, w.graph_repair, keep_local=1)
+    torch.cuda.synchronize()
+    return B, w, base, adj, entry, info
+
+
+def test_fullsize_knn_rows_sampled(full):
+    B, w, base, adj, entry, info = full
+    rows = np.random.default_rng(7).choice(w.base.shape[0], 12, replace=False).astype(np.int32)
+    print("case: full-size exact 64-NN of 12 sampled vertices", flush=True)
+    gids, gd = B.knn(base, base[torch.from_numpy(rows).long().cuda()], 65)
+    gids, gd = gids.cpu().numpy(), gd.cpu().numpy()
+    eids, ed = oracle.knn_self(w.base, rows, 64)
+    for i, v in enumerate(rows):
+        keep = gids[i] != v
+        np.testing.assert_array_equal(gids[i][keep][:64], eids[i])
+        np.testing.assert_array_equal(gd[i][keep][:64], ed[i])
+
+
+def test_fullsize_graph_properties(full):
+    B, w, base, adj, entry, info = full
+    a = adj.cpu().numpy()
+    n, R = a.shape
+    assert entry == oracle.medoid(w.base)
+    assert info["components"] == 256
+    assert ((a >= -1) & (a < n)).all()
+    valid = a >= 0
+    # padding only at the end of a row, no self loops, no repeated id in a row
+    assert (np.diff(valid.astype(np.int8), axis=1) <= 0).all()
+    assert not (a == np.arange(n)[:, None]).any()
+    srt = np.sort(np.where(valid, a, -1 - np.arange(R)[None, :]), axis=1)
+    assert not ((srt[:, 1:] == srt[:, :-1]) & (srt[:, 1:] >= 0)).any()
+    cnt, _ = oracle.reachable(a, entry)
+    assert cnt == n
+
+
+@pytest.mark.parametrize("M", [1, 2])
+def test_fullsize_search_sampled(full, M):
+    B, w, base, adj, entry, info = full
+    ix = B.Index(base, adj, entry)
+    q = torch.from_numpy(w.queries).cuda()
+    print(f"case: full-size search M={M} L=384 all 10000 queries", flush=True)
+    r = ix.search(q, 10, 384, M, stats=True, sync="adaptive", rho=0.8, staged=True)
+    ids, d, st = r.ids.cpu().numpy(), r.dists.cpu().numpy(), r.stats.cpu().numpy()
+    assert (st[:, 5] & 3 == 0).all()
+    # sorted by key, distinct, ids in range, no padding (the graph is connected)
+    assert (ids >= 0).all() and (ids < w.base.shape[0]).all()
+    keys = d.astype(np.float64) * 2**32 + ids
+    assert (np.diff(keys, axis=1) > 0).all()
+    sample = np.random.default_rng(3).choice(w.queries.shape[0], 60, replace=False)
+    # distances equal the oracle's distance of the returned ids
+    for qi in sample[:20]:
+        for j in range(10):
+            assert d[qi, j] == oracle.distance(w.queries[qi], w.base[ids[qi, j]])
+    # recall against the oracle's exact kNN of sampled queries, and dominance
+    gt, gd = oracle.knn(w.base, w.queries[sample], 10)
+    rec = oracle.recall(ids[sample], gt).mean()
+    print(f"   sampled recall@10 = {rec:.4f}", flush=True)
+    assert rec >= 0.97
+    assert (d[sample] >= gd).all()
