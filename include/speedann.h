@@ -98,10 +98,32 @@ void sa_default_params(sa_search_params *out);
  *   exclude_self when queries_dev == base_dev: row i skips base id i (graph construction)
  *   ids_dev      nq x k int32, dists_dev nq x k float32 (row-major); padded with
  *                (-1, +inf) when n (minus the excluded row) < k
- * 1 <= k <= 256.  Enqueued on hip_stream. */
+ * 1 <= k <= 256.  Same as sa_knn_ex with SA_KNN_AUTO.  Synchronous: it returns after the
+ * results are written. */
 int sa_knn(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float *queries_dev, int64_t nq,
            int64_t ldq, int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids_dev, float *dists_dev,
            void *hip_stream);
+
+/* Two ways to compute the same exact result:
+ *   SA_KNN_SCAN  double-precision accumulation on the vector units, any float data.
+ *   SA_KNN_MFMA  bf16 matrix-core products, only for integer-valued data: every base and
+ *                query coordinate an integer in [-255, 255], d <= 256 and k <= 128.  Then
+ *                the coordinates, products and partial sums are all exact (each sum stays
+ *                below 2^24 in magnitude), the squared distance |q|^2 + |x|^2 - 2 q.x is
+ *                formed in 32-bit integers and rounded once to float32, and the keys equal
+ *                the double-precision ones bit for bit.  It copies base and queries to a
+ *                temporary bf16 array (hipMalloc, freed before returning) and checks the
+ *                values on the device first.
+ *   SA_KNN_AUTO  SA_KNN_MFMA when the shape allows it and the check passes, else
+ *                SA_KNN_SCAN. */
+typedef enum { SA_KNN_AUTO = 0, SA_KNN_SCAN = 1, SA_KNN_MFMA = 2 } sa_knn_path;
+
+/* sa_knn with an explicit path.  SA_KNN_MFMA on data or shapes it cannot take exactly
+ * returns SA_EUNSUPPORTED.  *path_used_out (if not NULL) receives the path that ran
+ * (SA_KNN_SCAN or SA_KNN_MFMA; SA_KNN_AUTO when nq == 0).  Synchronous. */
+int sa_knn_ex(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float *queries_dev, int64_t nq,
+              int64_t ldq, int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids_dev, float *dists_dev,
+              int32_t path, int32_t *path_used_out, void *hip_stream);
 
 /* ------------------------------------------------------------------ graph construction
  * The paper searches a graph built offline (NSG, Sec. 2.2) and does not construct one.

@@ -19,7 +19,7 @@ SA_L2, SA_IP = 0, 1
 SYNC = {"bsp": 0, "static": 1, "adaptive": 2}
 QFLAG_MAX_STEPS, QFLAG_CAPACITY, QFLAG_SPILLED = 1, 2, 4
 
-EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_medoid", "sa_prune", "sa_reverse_edges",
+EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_medoid", "sa_prune", "sa_reverse_edges",
            "sa_repair", "sa_build_graph", "sa_index_create", "sa_index_destroy", "sa_search_workspace_bytes", "sa_search"]
 
 
@@ -51,6 +51,7 @@ def lib():
         L.sa_last_error.restype = C.c_char_p
         L.sa_default_params.argtypes = [C.POINTER(SearchParams)]
         L.sa_knn.argtypes = [vp, i64, i32, i64, vp, i64, i64, i32, i32, i32, vp, vp, vp]
+        L.sa_knn_ex.argtypes = [vp, i64, i32, i64, vp, i64, i64, i32, i32, i32, vp, vp, i32, C.POINTER(C.c_int32), vp]
         L.sa_medoid.argtypes = [vp, i64, i32, i64, C.POINTER(C.c_int32), vp]
         L.sa_prune.argtypes = [vp, i64, i32, i64, i32, vp, i32, i32, i32, vp, vp]
         L.sa_reverse_edges.argtypes = [vp, i64, i32, i64, i32, vp, i32, C.POINTER(C.c_int64), vp]
@@ -64,7 +65,7 @@ def lib():
         L.sa_search_workspace_bytes.argtypes = [vp, i64, i32, i32, i32, C.POINTER(SearchParams)]
         L.sa_search_workspace_bytes.restype = sz
         L.sa_search.argtypes = [vp, vp, i64, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp, sz, vp]
-        for name in ("sa_knn", "sa_medoid", "sa_prune", "sa_reverse_edges", "sa_repair", "sa_build_graph", "sa_index_create",
+        for name in ("sa_knn", "sa_knn_ex", "sa_medoid", "sa_prune", "sa_reverse_edges", "sa_repair", "sa_build_graph", "sa_index_create",
                      "sa_search"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -106,16 +107,28 @@ def pad_dim(x: torch.Tensor) -> torch.Tensor:
     return out
 
 
-def knn(base: torch.Tensor, queries: torch.Tensor, k: int, metric="l2", exclude_self=False, stream=None):
-    """Exact top-k by (distance, id) over all rows of base (linear scan on the GPU)."""
+KNN_PATHS = {"auto": 0, "scan": 1, "mfma": 2}
+
+
+def knn(base: torch.Tensor, queries: torch.Tensor, k: int, metric="l2", exclude_self=False, stream=None,
+        path="auto", return_path=False):
+    """Exact top-k by (distance, id) over all rows of base (linear scan on the GPU).
+
+    path: "scan" (double precision, any data), "mfma" (bf16 matrix cores, integer-valued
+    data only, exact), "auto" (mfma where it applies).  With return_path the path that
+    ran is returned as a third value."""
     base = pad_dim(_mat(base, "base"))
     queries = base if (exclude_self and queries is None) else pad_dim(_mat(queries, "queries"))
     nq = queries.shape[0]
     ids = torch.empty((nq, k), dtype=torch.int32, device=base.device)
     dists = torch.empty((nq, k), dtype=torch.float32, device=base.device)
-    _check(lib().sa_knn(base.data_ptr(), base.shape[0], base.shape[1], base.stride(0), queries.data_ptr(), nq,
-                        queries.stride(0), k, _metric(metric), int(exclude_self), ids.data_ptr(), dists.data_ptr(),
-                        _stream(stream)), "sa_knn")
+    used = C.c_int32(0)
+    _check(lib().sa_knn_ex(base.data_ptr(), base.shape[0], base.shape[1], base.stride(0), queries.data_ptr(), nq,
+                           queries.stride(0), k, _metric(metric), int(exclude_self), ids.data_ptr(),
+                           dists.data_ptr(), KNN_PATHS[path], C.byref(used), _stream(stream)), "sa_knn_ex")
+    if return_path:
+        names = {v: n for n, v in KNN_PATHS.items()}
+        return ids, dists, names[int(used.value)]
     return ids, dists
 
 

@@ -90,10 +90,12 @@ void sa_default_params(sa_search_params *out)
     out->staged = 1;
 }
 
-int sa_knn(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float *queries_dev, int64_t nq, int64_t ldq,
-           int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids_dev, float *dists_dev, void *hip_stream)
+int sa_knn_ex(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float *queries_dev, int64_t nq,
+              int64_t ldq, int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids_dev, float *dists_dev,
+              int32_t path, int32_t *path_used_out, void *hip_stream)
 {
     int rc;
+    if (path_used_out) *path_used_out = SA_KNN_AUTO;
     if ((rc = check_matrix(base_dev, n, d, ld, "base")) != SA_OK) return rc;
     if ((rc = check_matrix(queries_dev, nq, d, ldq, "queries")) != SA_OK) return rc;
     if (n >= (int64_t(1) << 31)) return set_error(SA_EINVAL, "n must be < 2^31");
@@ -101,9 +103,18 @@ int sa_knn(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float 
     if (metric != SA_L2 && metric != SA_IP) return set_error(SA_EINVAL, "unknown metric %d", metric);
     if (nq > 0 && (ids_dev == nullptr || dists_dev == nullptr)) return set_error(SA_EINVAL, "output is NULL");
     if (exclude_self && nq > n) return set_error(SA_EINVAL, "exclude_self needs the queries to be base rows");
+    if (path != SA_KNN_AUTO && path != SA_KNN_SCAN && path != SA_KNN_MFMA)
+        return set_error(SA_EINVAL, "unknown kNN path %d", path);
     if ((rc = check_device()) != SA_OK) return rc;
-    return launch_knn(base_dev, n, d, ld, queries_dev, nq, ldq, k, metric, exclude_self, ids_dev, dists_dev,
-                      (hipStream_t)hip_stream);
+    return launch_knn(base_dev, n, d, ld, queries_dev, nq, ldq, k, metric, exclude_self, ids_dev, dists_dev, path,
+                      path_used_out, (hipStream_t)hip_stream);
+}
+
+int sa_knn(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float *queries_dev, int64_t nq, int64_t ldq,
+           int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids_dev, float *dists_dev, void *hip_stream)
+{
+    return sa_knn_ex(base_dev, n, d, ld, queries_dev, nq, ldq, k, metric, exclude_self, ids_dev, dists_dev,
+                     SA_KNN_AUTO, nullptr, hip_stream);
 }
 
 int sa_medoid(const float *base_dev, int64_t n, int32_t d, int64_t ld, int32_t *entry_out, void *hip_stream)
@@ -184,7 +195,7 @@ int sa_build_graph(const float *base_dev, int64_t n, int32_t d, int64_t ld, int3
         if (cand) (void)hipFree(cand);
         return set_error(SA_ENOMEM, "build_graph: candidate lists do not fit");
     }
-    rc = launch_knn(base_dev, n, d, ld, base_dev, n, ld, knn_k, metric, 1, cand, cd, s);
+    rc = launch_knn(base_dev, n, d, ld, base_dev, n, ld, knn_k, metric, 1, cand, cd, SA_KNN_AUTO, nullptr, s);
     if (rc == SA_OK) rc = prune_device(base_dev, n, d, ld, metric, cand, knn_k, R, prune, adj_dev, s);
     if (rc == SA_OK) {
         hipError_t e = hipStreamSynchronize(s);

@@ -1,0 +1,362 @@
+// Exact k nearest neighbours on the matrix cores for integer-valued data, and the choice
+// between this path and the double-precision scan of knn.hip.
+//
+// Exactness.  When every coordinate is an integer in [-255, 255] and d <= 256, bf16 holds
+// each coordinate exactly, each product is an integer below 2^16 and every partial sum of
+// a dot product stays below 256 * 255^2 < 2^24 in magnitude, so the fp32 accumulators of
+// v_mfma_f32_16x16x32_bf16 hold the exact integer dot product whatever order the
+// additions take.  The squared distance |q|^2 + |x|^2 - 2 q.x (or -q.x for the inner
+// product) is then formed in 32-bit integers and rounded once to float, which is the key
+// the scan produces, bit for bit.
+//
+// Work split.  A workgroup of four wavefronts owns MQ = 64 queries, whose bf16 rows stay
+// in registers as the A operands (4 row blocks x d/32 k-steps).  The base streams in
+// tiles of MT = 64 rows; wavefront w multiplies rows 16w .. 16w+15 of each tile against
+// all 64 queries, loading its B operands from memory straight into a ring of registers
+// that runs one or two tiles ahead of the products.
+//
+// Selection.  A product passes a cheap integer test first: u <= B_q with u = |x|^2 - 2 q.x
+// and B_q = T_q - |q|^2, where T_q bounds from above every integer distance whose float
+// rounding does not exceed the query's current k-th distance.  Only passing products
+// build a 64-bit key and enter the query's LDS buffer, which is sorted and merged into
+// the query's top-k list as in the scan.
+#include "knn_select.h"
+
+#include <climits>
+
+namespace sa {
+namespace {
+
+using knn_detail::flush_query;
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int MQ = 64;                 // queries per workgroup
+constexpr int MT = 64;                 // base rows per tile
+constexpr int MNT = 256;               // four wavefronts
+constexpr int MBUF = 128;              // candidates buffered per query; flushed when > MBUF - MT
+constexpr int32_t NORM_PAD = 1 << 30;  // norm of padding rows
+
+struct PrepArgs {
+    const float *x;
+    int64_t n, ld, rows;  // rows: n rounded up to the tile size
+    int32_t d, dpad, metric;
+    __bf16 *out;          // rows x dpad
+    int32_t *norm;        // rows
+    int32_t *bad;
+};
+
+// One wavefront per row: the bf16 copy (zero padded to dpad columns and `rows` rows), the
+// exact integer squared norm (0 for the inner product, NORM_PAD for padding rows), and a
+// flag raised by any value that is not an integer in [-255, 255] (NaN included).
+__global__ void __launch_bounds__(256) knn_prep_kernel(PrepArgs P)
+{
+    const int lane = __lane_id();
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= P.rows) return;
+    int sum = 0;
+    bool bad = false;
+    for (int c = lane; c < P.dpad; c += 64) {
+        float v = 0.f;
+        if (row < P.n && c < P.d) v = P.x[row * P.ld + c];
+        const bool ok = fabsf(v) <= 255.f && v == rintf(v);
+        bad |= !ok;
+        const int iv = ok ? (int)v : 0;
+        sum += iv * iv;
+        P.out[row * P.dpad + c] = (__bf16)(ok ? v : 0.f);
+    }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if (bad) atomicOr(P.bad, 1);
+    if (lane == 0) P.norm[row] = row < P.n ? (P.metric == SA_L2 ? sum : 0) : NORM_PAD;
+}
+
+// Upper bound, minus |q|^2, on the integer distances whose float rounding is at most the
+// distance of key thr.  Distances here are roundings of integers, so the float is
+// integral; below 2^24 it is exact, above it one unit in the last place covers every
+// integer that rounds down onto it.  INT_MAX while the list is not full.
+__device__ inline int prefilter_bound(uint64_t thr, int32_t qnorm)
+{
+    if (thr == KEY_EMPTY) return INT_MAX;
+    const float f = key_dist(thr);
+    int64_t t = (int64_t)f;
+    const float a = fabsf(f);
+    if (a >= 16777216.f) t += int64_t(1) << ((int)((__float_as_uint(a) >> 23) & 0xFF) - 127 - 23);
+    t -= qnorm;
+    return t > INT_MAX ? INT_MAX : (int)t;
+}
+
+struct MArgs {
+    const __bf16 *xb;    // base rows, xrows x dpad
+    const int32_t *xn;   // their norms
+    const __bf16 *qb;    // query rows, a multiple of MQ rows x dpad
+    const int32_t *qn;
+    int64_t n, nq, xrows;
+    int32_t dpad, k, kpad, exclude_self;
+    int32_t *ids;
+    float *dists;
+};
+
+template <int KS, bool L2>
+__global__ void __launch_bounds__(MNT) knn_mfma_kernel(MArgs A)
+{
+    constexpr int NB = KS <= 4 ? 3 : 2;  // register ring: tiles in flight + the one in use
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    uint64_t *top = reinterpret_cast<uint64_t *>(smem);   // [MQ][kpad] sorted best keys
+    uint64_t *buf = top + (size_t)MQ * A.kpad;             // [MQ][MBUF] unsorted candidates
+    uint64_t *thr = buf + (size_t)MQ * MBUF;               // [MQ] k-th key (or empty)
+    int *cnt = reinterpret_cast<int *>(thr + MQ);          // [MQ] buffered candidates
+    int *len = cnt + MQ;                                   // [MQ] length of top
+    int *bnd = len + MQ;                                   // [MQ] B_q of the prefilter
+    int *qns = bnd + MQ;                                   // [MQ] |q|^2
+    int *need = qns + MQ;  // 1 + index of the last tile in which a buffer passed MBUF - MT
+
+    const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+    const int64_t q0 = (int64_t)blockIdx.x * MQ;
+    for (int i = tid; i < MQ; i += MNT) {
+        cnt[i] = 0;
+        len[i] = 0;
+        thr[i] = KEY_EMPTY;
+        bnd[i] = q0 + i < A.nq ? INT_MAX : INT_MIN;  // padding queries take nothing
+        qns[i] = A.qn[q0 + i];
+    }
+    if (tid == 0) *need = 0;
+
+    bf16x8 a[4][KS];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const __bf16 *p = A.qb + (q0 + rb * 16 + (lane & 15)) * A.dpad + 8 * (lane >> 4);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) a[rb][ks] = *reinterpret_cast<const bf16x8 *>(p + ks * 32);
+    }
+    __syncthreads();
+    // lane holds output rows 4 (lane / 16) + r of each row block, column lane % 16
+    int bq[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bq[rb][r] = bnd[rb * 16 + 4 * (lane >> 4) + r];
+
+    const int64_t ntile = A.xrows / MT;
+    bf16x8 b[NB][KS];
+    int bn[NB];
+#pragma unroll
+    for (int j = 0; j < NB - 1; ++j) {
+        const int64_t row = (j < ntile ? j : ntile - 1) * MT + 16 * w + (lane & 15);
+        const __bf16 *p = A.xb + row * A.dpad + 8 * (lane >> 4);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) b[j][ks] = *reinterpret_cast<const bf16x8 *>(p + ks * 32);
+        bn[j] = A.xn[row];
+    }
+
+    for (int64_t t0 = 0; t0 < ntile; t0 += NB) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int64_t t = t0 + j;
+            if (t >= ntile) break;
+            {
+                // refill the slot freed by the previous tile; past the end, reload the last tile
+                const int jn = (j + NB - 1) % NB;
+                const int64_t tn = t + NB - 1 < ntile ? t + NB - 1 : ntile - 1;
+                const int64_t row = tn * MT + 16 * w + (lane & 15);
+                const __bf16 *p = A.xb + row * A.dpad + 8 * (lane >> 4);
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) b[jn][ks] = *reinterpret_cast<const bf16x8 *>(p + ks * 32);
+                bn[jn] = A.xn[row];
+            }
+            f32x4 acc[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) acc[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb][ks], b[j][ks], acc[rb], 0, 0, 0);
+            const int64_t col = t * MT + 16 * w + (lane & 15);
+            const int nx = bn[j];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int dneg = (int)(-acc[rb][r]);  // -q.x, exact
+                    const int u = L2 ? nx + 2 * dneg : dneg;
+                    if (u <= bq[rb][r]) {
+                        const int row = rb * 16 + 4 * (lane >> 4) + r;
+                        if (col < A.n && !(A.exclude_self && col == q0 + row)) {
+                            const uint64_t key = make_key((float)(qns[row] + u), (int32_t)col);
+                            if (key < thr[row]) {
+                                const int pos = atomicAdd(&cnt[row], 1);
+                                buf[(size_t)row * MBUF + pos] = key;
+                                if (pos + 1 > MBUF - MT) *need = (int)(t + 1);
+                            }
+                        }
+                    }
+                }
+            __syncthreads();
+            // every wavefront reads the same value: a later tile can only write after the
+            // barrier that follows a flush
+            const bool last = t + 1 == ntile;
+            if (*need == (int)(t + 1) || last) {
+                for (int qr = w; qr < MQ; qr += MNT / 64) {
+                    const int c = cnt[qr];
+                    if (c == 0) continue;
+                    flush_query(top + (size_t)qr * A.kpad, &len[qr], buf + (size_t)qr * MBUF, c, A.k);
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane == 0) {
+                        cnt[qr] = 0;
+                        if (len[qr] >= A.k) {
+                            const uint64_t th = top[(size_t)qr * A.kpad + A.k - 1];
+                            thr[qr] = th;
+                            bnd[qr] = prefilter_bound(th, qns[qr]);
+                        }
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) bq[rb][r] = bnd[rb * 16 + 4 * (lane >> 4) + r];
+            }
+        }
+    }
+    for (int i = tid; i < MQ * A.k; i += MNT) {
+        const int qr = i / A.k, j = i % A.k;
+        const int64_t qg = q0 + qr;
+        if (qg >= A.nq) continue;
+        if (j < len[qr]) {
+            const uint64_t key = top[(size_t)qr * A.kpad + j];
+            A.ids[qg * A.k + j] = key_id(key);
+            A.dists[qg * A.k + j] = key_dist(key);
+        } else {
+            A.ids[qg * A.k + j] = -1;
+            A.dists[qg * A.k + j] = __builtin_inff();
+        }
+    }
+}
+
+using MKernel = void (*)(MArgs);
+
+template <int KS>
+MKernel pick(int metric)
+{
+    return metric == SA_L2 ? knn_mfma_kernel<KS, true> : knn_mfma_kernel<KS, false>;
+}
+
+MKernel pick_kernel(int ks, int metric)
+{
+    switch (ks) {
+    case 1: return pick<1>(metric);
+    case 2: return pick<2>(metric);
+    case 3: return pick<3>(metric);
+    case 4: return pick<4>(metric);
+    case 6: return pick<6>(metric);
+    case 8: return pick<8>(metric);
+    default: return nullptr;
+    }
+}
+
+struct DeviceBlock {
+    void *p = nullptr;
+    ~DeviceBlock()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Runs the matrix-core path if every coordinate qualifies; *ran tells whether it did.
+int launch_knn_mfma(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq,
+                    int64_t ldq, int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists,
+                    bool *ran, hipStream_t s)
+{
+    *ran = false;
+    int ks = (d + 31) / 32;
+    if (ks == 5) ks = 6;
+    if (ks == 7) ks = 8;
+    const int dpad = 32 * ks;
+    const int64_t xrows = (n + MT - 1) / MT * MT;
+    const bool shared_q = queries == base && ldq == ld && nq <= n;
+    const int64_t qrows = shared_q ? xrows : (nq + MQ - 1) / MQ * MQ;
+    const size_t xb_bytes = align256((size_t)xrows * dpad * 2), xn_bytes = align256((size_t)xrows * 4);
+    const size_t qb_bytes = shared_q ? 0 : align256((size_t)qrows * dpad * 2);
+    const size_t qn_bytes = shared_q ? 0 : align256((size_t)qrows * 4);
+    DeviceBlock mem;
+    if (hipMalloc(&mem.p, xb_bytes + xn_bytes + qb_bytes + qn_bytes + 256) != hipSuccess) {
+        (void)hipGetLastError();
+        mem.p = nullptr;
+        return set_error(SA_ENOMEM, "hipMalloc of the bf16 copies failed");
+    }
+    unsigned char *m = static_cast<unsigned char *>(mem.p);
+    __bf16 *xb = reinterpret_cast<__bf16 *>(m);
+    int32_t *xn = reinterpret_cast<int32_t *>(m + xb_bytes);
+    __bf16 *qb = shared_q ? xb : reinterpret_cast<__bf16 *>(m + xb_bytes + xn_bytes);
+    int32_t *qn = shared_q ? xn : reinterpret_cast<int32_t *>(m + xb_bytes + xn_bytes + qb_bytes);
+    int32_t *bad = reinterpret_cast<int32_t *>(m + xb_bytes + xn_bytes + qb_bytes + qn_bytes);
+
+    SA_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+    PrepArgs P{base, n, ld, xrows, d, dpad, metric, xb, xn, bad};
+    hipLaunchKernelGGL(knn_prep_kernel, dim3((unsigned)((xrows + 3) / 4)), dim3(256), 0, s, P);
+    SA_HIP(hipGetLastError());
+    if (!shared_q) {
+        PrepArgs Q{queries, nq, ldq, qrows, d, dpad, metric, qb, qn, bad};
+        hipLaunchKernelGGL(knn_prep_kernel, dim3((unsigned)((qrows + 3) / 4)), dim3(256), 0, s, Q);
+        SA_HIP(hipGetLastError());
+    }
+    int32_t flag = 0;
+    SA_HIP(hipMemcpyAsync(&flag, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+    if (flag) return SA_OK;
+
+    MArgs A;
+    A.xb = xb; A.xn = xn; A.qb = qb; A.qn = qn;
+    A.n = n; A.nq = nq; A.xrows = xrows;
+    A.dpad = dpad; A.k = k; A.kpad = (k + 63) / 64 * 64; A.exclude_self = exclude_self;
+    A.ids = ids; A.dists = dists;
+    const size_t lds = 8ull * MQ * A.kpad + 8ull * MQ * MBUF + 8ull * MQ + 4ull * 4 * MQ + 16;
+    if (lds > 160u * 1024u) return set_error(SA_EINVAL, "k=%d needs too much LDS", k);
+    MKernel kern = pick_kernel(ks, metric);
+    if (!kern) return set_error(SA_EUNSUPPORTED, "d=%d", d);
+    SA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    hipLaunchKernelGGL(kern, dim3((unsigned)((nq + MQ - 1) / MQ)), dim3(MNT), lds, s, A);
+    SA_HIP(hipGetLastError());
+    SA_HIP(hipStreamSynchronize(s));
+    *ran = true;
+    return SA_OK;
+}
+
+}  // namespace
+
+int launch_knn(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq, int64_t ldq,
+               int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists, int32_t path,
+               int32_t *path_used, hipStream_t stream)
+{
+    if (path_used) *path_used = SA_KNN_AUTO;
+    if (path != SA_KNN_AUTO && path != SA_KNN_SCAN && path != SA_KNN_MFMA)
+        return set_error(SA_EINVAL, "unknown kNN path %d", path);
+    if (nq == 0) return SA_OK;
+    const bool shape_ok = n >= 1 && d <= 256 && k <= 128;
+    if (path == SA_KNN_MFMA && !shape_ok)
+        return set_error(SA_EUNSUPPORTED, "the MFMA kNN path needs n >= 1, d <= 256 and k <= 128 (n=%lld, d=%d, k=%d)",
+                         (long long)n, d, k);
+    if (path != SA_KNN_SCAN && shape_ok) {
+        bool ran = false;
+        const int rc = launch_knn_mfma(base, n, d, ld, queries, nq, ldq, k, metric, exclude_self, ids, dists, &ran,
+                                       stream);
+        if (rc != SA_OK) return rc;
+        if (ran) {
+            if (path_used) *path_used = SA_KNN_MFMA;
+            return SA_OK;
+        }
+        if (path == SA_KNN_MFMA)
+            return set_error(SA_EUNSUPPORTED, "the MFMA kNN path needs every coordinate to be an integer in [-255, 255]");
+    }
+    const int rc = launch_knn_scan(base, n, d, ld, queries, nq, ldq, k, metric, exclude_self, ids, dists, stream);
+    if (rc != SA_OK) return rc;
+    SA_HIP(hipStreamSynchronize(stream));
+    if (path_used) *path_used = SA_KNN_SCAN;
+    return SA_OK;
+}
+
+}  // namespace sa

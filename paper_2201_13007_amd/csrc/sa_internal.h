@@ -54,8 +54,15 @@ __host__ __device__ inline float key_dist(uint64_t k) { return ordered_to_float(
 
 // ---------------------------------------------------------------- launchers
 
+// Exact kNN through the path chosen by `path` (sa_knn_path); *path_used gets the one that
+// ran.  Synchronous.
 int launch_knn(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq, int64_t ldq,
-               int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists, hipStream_t stream);
+               int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists, int32_t path,
+               int32_t *path_used, hipStream_t stream);
+// The double-precision scan (any data); enqueued only.
+int launch_knn_scan(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq,
+                    int64_t ldq, int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists,
+                    hipStream_t stream);
 
 struct SearchLaunch {
     const float *vec;

@@ -104,9 +104,10 @@ def gist_like(n: int = 1_000_000, nq: int = 20_000, d: int = 960, ncomp: int = 1
                                   "base_labels": lb, "query_labels": lq})
 
 
-def integer_grid(n: int, d: int, nq: int, hi: int = 16, config: int = 90) -> Workload:
-    """Small-integer-valued vectors (uniform over 0..hi-1) for order-independent exact
-    distances in tests; duplicates and exact distance ties are common by design."""
-    base = rng(config, S_BASE_NOISE).integers(0, hi, size=(n, d)).astype(np.float32)
-    queries = rng(config, S_Q_NOISE).integers(0, hi, size=(nq, d)).astype(np.float32)
+def integer_grid(n: int, d: int, nq: int, hi: int = 16, config: int = 90, lo: int = 0) -> Workload:
+    """Integer-valued vectors (uniform over lo..hi-1) for order-independent exact
+    distances in tests; with a narrow range, duplicates and exact distance ties are
+    common by design."""
+    base = rng(config, S_BASE_NOISE).integers(lo, hi, size=(n, d)).astype(np.float32)
+    queries = rng(config, S_Q_NOISE).integers(lo, hi, size=(nq, d)).astype(np.float32)
     return Workload(f"int-grid-{n}x{d}", base, queries, "l2", 10, 16, 16, "knn", False, {"config": config})

@@ -73,6 +73,9 @@ def test_validation_errors_without_device(B):
     assert L.sa_knn(fake, 10, 32, 32, fake, 3, 32, 300, 0, 0, fake, fake, None) == -1
     assert L.sa_knn(fake + 4, 10, 32, 32, fake, 3, 32, 5, 0, 0, fake, fake, None) == -1
     assert "aligned" in _err(B)
+    used = C.c_int32(7)
+    assert L.sa_knn_ex(fake, 10, 32, 32, fake, 3, 32, 5, 0, 0, fake, fake, 3, C.byref(used), None) == -1
+    assert "path" in _err(B) and used.value == 0
     assert L.sa_prune(fake, 10, 32, 32, 0, fake, 65, 16, 1, fake, None) == -1
     e = C.c_int32(0)
     assert L.sa_build_graph(fake, 1, 32, 32, 0, 16, 16, 0, 0, 1, 4, 4, fake, C.byref(e), None, None, None) == -1

@@ -30,14 +30,24 @@ def full():
 def test_fullsize_knn_rows_sampled(full):
     B, w, base, adj, entry, info = full
     rows = np.random.default_rng(7).choice(w.base.shape[0], 12, replace=False).astype(np.int32)
-    print("case: full-size exact 64-NN of 12 sampled vertices", flush=True)
-    gids, gd = B.knn(base, base[torch.from_numpy(rows).long().cuda()], 65)
-    gids, gd = gids.cpu().numpy(), gd.cpu().numpy()
     eids, ed = oracle.knn_self(w.base, rows, 64)
-    for i, v in enumerate(rows):
-        keep = gids[i] != v
-        np.testing.assert_array_equal(gids[i][keep][:64], eids[i])
-        np.testing.assert_array_equal(gd[i][keep][:64], ed[i])
+    # the self-join that graph construction runs (matrix-core path on these integer data)
+    print("case: full-size 64-NN self-join, 12 sampled rows checked", flush=True)
+    ids, dd, used = B.knn(base, None, 64, exclude_self=True, return_path=True)
+    assert used == "mfma"
+    ids, dd = ids.cpu().numpy(), dd.cpu().numpy()
+    np.testing.assert_array_equal(ids[rows], eids)
+    np.testing.assert_array_equal(dd[rows], ed)
+    del ids, dd
+    # both paths on the sampled rows as separate queries (their own id comes first)
+    for path in ("mfma", "scan"):
+        print(f"case: full-size exact 65-NN of 12 sampled vertices, path={path}", flush=True)
+        gids, gd = B.knn(base, base[torch.from_numpy(rows).long().cuda()], 65, path=path)
+        gids, gd = gids.cpu().numpy(), gd.cpu().numpy()
+        for i, v in enumerate(rows):
+            keep = gids[i] != v
+            np.testing.assert_array_equal(gids[i][keep][:64], eids[i])
+            np.testing.assert_array_equal(gd[i][keep][:64], ed[i])
 
 
 def test_fullsize_graph_properties(full):

@@ -85,6 +85,91 @@ def test_knn_ip_and_short(B):
     np.testing.assert_array_equal(host(d), ed)
 
 
+# ------------------------------------------------------------------ exact kNN on the matrix cores
+# Integer-valued data take the bf16 MFMA path under "auto"; its keys must equal the
+# oracle's double-precision ones bit for bit.
+
+def _extremes(w):
+    # all-255 and all-(-255) rows: at d = 256 the dot products reach 256 * 255^2, just
+    # under 2^24, and the squared distances reach 256 * 510^2, where float rounds
+    base, q = w.base.copy(), w.queries.copy()
+    base[0], base[1], q[0], q[1] = 255.0, -255.0, 255.0, -255.0
+    return base, q
+
+
+@pytest.mark.parametrize("metric", ["l2", "ip"])
+@pytest.mark.parametrize("d", [4, 36, 100, 128, 160, 224, 256])
+def test_knn_mfma_shapes(B, d, metric):
+    w = synth.integer_grid(1037, d, 70, lo=-255, hi=256, config=91)
+    base, q = _extremes(w)
+    for k in (1, 10, 64, 128):
+        print(f"case: knn mfma d={d} {metric} k={k} n=1037 nq=70", flush=True)
+        ids, dd, path = B.knn(dev(base), dev(q), k, metric=metric, return_path=True)
+        assert path == "mfma"
+        eids, ed = oracle.knn(base, q, k, metric=metric)
+        np.testing.assert_array_equal(host(ids), eids)
+        np.testing.assert_array_equal(host(dd), ed)
+
+
+def test_knn_mfma_self_join_ties(B):
+    # values 0..3: exact ties everywhere, resolved by id; self rows excluded
+    w = synth.integer_grid(2500, 32, 1, hi=4, config=92)
+    print("case: knn mfma self-join 2500x32 k=64", flush=True)
+    ids, dd, path = B.knn(dev(w.base), None, 64, exclude_self=True, return_path=True)
+    assert path == "mfma"
+    eids, ed = oracle.knn(w.base, w.base, 64, exclude_self=True)
+    np.testing.assert_array_equal(host(ids), eids)
+    np.testing.assert_array_equal(host(dd), ed)
+    # fewer rows than k: padded
+    ids, dd, path = B.knn(dev(w.base[:40]), None, 64, exclude_self=True, return_path=True)
+    assert path == "mfma"
+    eids, ed = oracle.knn(w.base[:40], w.base[:40], 64, exclude_self=True)
+    np.testing.assert_array_equal(host(ids), eids)
+    np.testing.assert_array_equal(host(dd), ed)
+
+
+def test_knn_paths_agree_sift(B):
+    w = synth.sift_like(n=20_000, nq=200)
+    eids, ed = oracle.knn(w.base, w.queries, 100)
+    for path in ("mfma", "scan"):
+        print(f"case: knn sift 20000x128 k=100 path={path}", flush=True)
+        ids, dd, used = B.knn(dev(w.base), dev(w.queries), 100, path=path, return_path=True)
+        assert used == path
+        np.testing.assert_array_equal(host(ids), eids)
+        np.testing.assert_array_equal(host(dd), ed)
+    rows = np.arange(0, 20_000, 97, dtype=np.int32)
+    print("case: knn sift self-join k=64 sampled rows", flush=True)
+    ids, dd = B.knn(dev(w.base), None, 64, exclude_self=True)
+    sids, sd = oracle.knn_self(w.base, rows, 64)
+    np.testing.assert_array_equal(host(ids)[rows], sids)
+    np.testing.assert_array_equal(host(dd)[rows], sd)
+
+
+def test_knn_path_selection(B):
+    w = synth.tiny()  # float data: the scan
+    print("case: knn path selection", flush=True)
+    ids, dd, used = B.knn(dev(w.base), dev(w.queries), 10, return_path=True)
+    assert used == "scan"
+    with pytest.raises(B.SpeedAnnError, match="integer"):
+        B.knn(dev(w.base), dev(w.queries), 10, path="mfma")
+    g = synth.integer_grid(700, 16, 9, config=93)
+    for base, q, k, why in ((g.base * 0.5, g.queries, 10, "integer"),       # half-integers
+                            (g.base + 250.0, g.queries, 10, "integer"),     # beyond 255
+                            (g.base, g.queries, 129, "k <= 128")):
+        ids, dd, used = B.knn(dev(base), dev(q), k, return_path=True)
+        assert used == "scan"
+        eids, ed = oracle.knn(base, q, k)
+        np.testing.assert_array_equal(host(ids), eids)
+        np.testing.assert_array_equal(host(dd), ed)
+        with pytest.raises(B.SpeedAnnError, match=why):
+            B.knn(dev(base), dev(q), k, path="mfma")
+    wide = synth.integer_grid(300, 260, 4, config=94)
+    ids, dd, used = B.knn(dev(wide.base), dev(wide.queries), 10, return_path=True)
+    assert used == "scan"
+    with pytest.raises(B.SpeedAnnError, match="d <= 256"):
+        B.knn(dev(wide.base), dev(wide.queries), 10, path="mfma")
+
+
 # ------------------------------------------------------------------ graph construction
 
 def test_medoid(B):
