@@ -1,6 +1,6 @@
 // Host side of the search: parameter resolution, LDS layout, workspace sizing and the
-// launch of the single-worker or multi-worker kernels (search_single.hip,
-// search_multi.hip; the kernel body is in search_body.h).
+// launch of the single-worker kernel (search_single.hip) or of the general kernel
+// (search_multi.hip, whose body is in search_body.h).
 #include "search_body.h"
 
 namespace sa {
@@ -42,6 +42,11 @@ int ilog2_exact(int64_t v)
     return r;
 }
 
+// One worker with no LDS table runs the single-worker kernel, whose workspace table holds
+// 32-bit entries (id + 1) and needs no claim order; every other case runs the general
+// kernel with 64-bit entries that carry the claim tag.
+bool compact_table(int M, int llog2) { return M == 1 && llog2 == 0; }
+
 void resolve_params(const sa_search_params &in, int L, int M, int R, int &llog2, int &glog2, int &max_sub)
 {
     max_sub = in.max_substeps > 0 ? in.max_substeps : (1 << 22);
@@ -51,13 +56,17 @@ void resolve_params(const sa_search_params &in, int L, int M, int R, int &llog2,
     if (in.ws_hash_slots > 0) glog2 = ilog2_exact(in.ws_hash_slots);
     else {
         // the visited set holds at most 1 + E * R vertices after E expansions, and E stays
-        // close to L; 64 L slots keep three quarters of the table above 1.5 L * 32, and
-        // 8 M R more cover the M R vertices one local step may add on top
-        int64_t want = 64ll * L + 8ll * M * R;
+        // close to L.  The single-worker table (4-byte entries) takes 32 L slots: its
+        // three-quarter limit sits near 24 L, several times the 8 L or so a search visits
+        // at these R; the general table keeps 64 L.  8 M R more cover the M R vertices one
+        // local step may add on top.
+        int64_t want = (compact_table(M, llog2) ? 32ll : 64ll) * L + 8ll * M * R;
         if (want < 4096) want = 4096;
         glog2 = ilog2_exact(want);
     }
 }
+
+size_t bytes_per_slot(int M, int llog2) { return compact_table(M, llog2) ? 8 : 16; }
 
 }  // namespace
 
@@ -65,7 +74,7 @@ size_t search_workspace_bytes(int64_t nq, int32_t L, int32_t M, const sa_search_
 {
     int llog2, glog2, max_sub;
     resolve_params(p, L, M, R, llog2, glog2, max_sub);
-    return (size_t)nq * ((size_t)16 << glog2);
+    return (size_t)nq * (bytes_per_slot(M, llog2) << glog2);
 }
 
 int launch_search(const SearchLaunch &a, hipStream_t stream)
@@ -79,7 +88,7 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
         return set_error(SA_EINVAL, "lds_hash_slots too small for M * R new vertices per local step");
     if ((int64_t(1) << glog2) * 3 / 4 < (int64_t)a.M * a.R + 1)
         return set_error(SA_EINVAL, "ws_hash_slots too small for M * R new vertices per local step");
-    const size_t need = (size_t)a.nq * ((size_t)16 << glog2);
+    const size_t need = (size_t)a.nq * (bytes_per_slot(a.M, llog2) << glog2);
     if (a.ws_bytes < need)
         return set_error(SA_ECAPACITY, "workspace of %zu bytes is smaller than the %zu bytes needed", a.ws_bytes, need);
     if (a.workspace == nullptr && need > 0) return set_error(SA_EINVAL, "workspace is NULL");
@@ -101,7 +110,8 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     A.o_hash = Y.o_hash;
     if (a.nq == 0) return SA_OK;
     if (a.d > 1024) return set_error(SA_EUNSUPPORTED, "d=%d exceeds 1024", a.d);
-    return a.M == 1 ? launch_search_single(A, a.nq, Y.total, stream) : launch_search_multi(A, a.nq, a.M, Y.total, stream);
+    if (compact_table(a.M, llog2)) return launch_search_single(A, a.nq, stream);
+    return launch_search_multi(A, a.nq, a.M, Y.total, stream);
 }
 
 }  // namespace sa

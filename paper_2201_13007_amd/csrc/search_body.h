@@ -830,7 +830,7 @@ __device__ __forceinline__ void search_body(const KArgs &A)
 
 }  // namespace search_detail
 
-int launch_search_single(const search_detail::KArgs &A, int64_t nq, uint32_t lds, hipStream_t s);
+int launch_search_single(const search_detail::KArgs &A, int64_t nq, hipStream_t s);
 int launch_search_multi(const search_detail::KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s);
 
 }  // namespace sa

@@ -1,5 +1,5 @@
-// Search kernels with two or more workers (M >= 2), one wavefront per worker; see
-// search_body.h.
+// The general search kernel, one wavefront per worker (see search_body.h): every case
+// with two or more workers, and one worker with an LDS visited table.
 #include "search_body.h"
 
 namespace sa {

@@ -1,52 +1,424 @@
-// Search kernels with one worker (M = 1): Algorithm 1 run as Algorithm 3 with T = 1.
-// One 64-lane workgroup per query; see search_body.h.
+// Search with one worker (M = 1) and the visited set in the workspace: Algorithm 1, with
+// the bookkeeping of Algorithm 3 at T = 1.  With a single worker the merge of Algorithm 3
+// leaves the queue as it is, so the schedule (Algorithm 2) only moves the counters of
+// global steps and merges.
+//
+// One 64-lane workgroup per query and no barrier.  Everything is sized for occupancy:
+// the fewer registers a query needs, the more queries each SIMD keeps in flight to cover
+// the latency of the random reads.
+//
+// Queue.  NI = ceil(L / 64) slots per lane hold the sorted 64-bit keys (order-preserving
+// distance bits, id); entry p sits in slot p / 64 of lane p % 64.  The CHECKED flags are
+// wave-uniform 64-bit masks, one per slot, so finding the first unchecked entry is scalar
+// work.  An insertion moves every entry at or after the insertion point up by one lane
+// with a DPP wavefront shift, carrying lane 63 into lane 0 of the next slot.
+//
+// Visited set.  Open addressing over 32-bit entries (id + 1; zero is empty) in the
+// query's workspace region, claimed with compare-and-swap.  The slots a query fills are
+// listed after the table and zeroed again before it ends.
+//
+// Distances.  LPV lanes share one vector, each lane four float4 chunks (c = g, g + LPV,
+// ...), accumulated in double precision, summed into the group's last lane by DPP row
+// shifts and broadcasts, and rounded once to float.  The query row sits in LDS.
 #include "search_body.h"
 
 namespace sa {
-namespace search_detail {
+namespace single_detail {
 
-template <int LPV, int CPL, int NI>
-__global__ void __launch_bounds__(64) search_single(KArgs A)
+using search_detail::KArgs;
+using search_detail::NO_SLOT;
+using search_detail::hash_slot;
+using search_detail::lanemask_lt;
+using search_detail::rdlane64;
+
+constexpr int DPP_ROW_SHR = 0x110;     // + n: row_shr:n
+constexpr int DPP_WAVE_SHR1 = 0x138;   // wave_shr:1
+constexpr int DPP_ROW_BCAST15 = 0x142;
+constexpr int DPP_ROW_BCAST31 = 0x143;
+
+// lanes whose DPP source is invalid (outside the row or the enabled rows) keep `old`
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v, uint32_t old)
 {
-    search_body<LPV, CPL, NI, false>(A);
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWMASK, 0xF, false);
 }
 
-template <int LPV, int CPL, int NI>
-hipError_t launch1(const KArgs &A, int64_t nq, uint32_t lds, hipStream_t s)
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double v)
 {
-    auto k = search_single<LPV, CPL, NI>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = dpp32<CTRL, ROWMASK>((uint32_t)b, 0u);
+    const uint32_t hi = dpp32<CTRL, ROWMASK>((uint32_t)(b >> 32), 0u);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// sum of each group of LPV lanes, left in the group's last lane
+template <int LPV>
+__device__ __forceinline__ double group_sum(double v)
+{
+    if constexpr (LPV >= 2) v += dpp_f64<DPP_ROW_SHR + 1>(v);
+    if constexpr (LPV >= 4) v += dpp_f64<DPP_ROW_SHR + 2>(v);
+    if constexpr (LPV >= 8) v += dpp_f64<DPP_ROW_SHR + 4>(v);
+    if constexpr (LPV >= 16) v += dpp_f64<DPP_ROW_SHR + 8>(v);
+    if constexpr (LPV >= 32) v += dpp_f64<DPP_ROW_BCAST15, 0xA>(v);
+    if constexpr (LPV >= 64) v += dpp_f64<DPP_ROW_BCAST31, 0xC>(v);
+    return v;
+}
+
+// lane l gets lane l - 1 of v; lane 0 gets carry
+__device__ __forceinline__ uint64_t shift_up64(uint64_t v, uint64_t carry)
+{
+    const uint32_t lo = dpp32<DPP_WAVE_SHR1>((uint32_t)v, (uint32_t)carry);
+    const uint32_t hi = dpp32<DPP_WAVE_SHR1>((uint32_t)(v >> 32), (uint32_t)(carry >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// bits [0, n) set, n in [0, 64]
+__device__ __forceinline__ uint64_t low_bits(int n)
+{
+    return n <= 0 ? 0ull : (n >= 64 ? ~0ull : (~0ull >> (64 - n)));
+}
+
+template <int NI>
+struct Queue {
+    uint64_t k[NI];    // keys; KEY_EMPTY past the end
+    uint64_t chk[NI];  // CHECKED bits (wave-uniform)
+    int len;
+};
+
+template <int NI>
+__device__ __forceinline__ int first_unchecked(const Queue<NI> &Q)
+{
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const uint64_t b = low_bits(Q.len - 64 * i) & ~Q.chk[i];
+        if (b) return 64 * i + __builtin_ctzll(b);
+    }
+    return 64 * NI;
+}
+
+// Uniform position p: the key is read with a lane read in the branch of its slot, and a
+// flag is set by a masked update of every slot.  Folding either into an access indexed by
+// p / 64 would make the compiler move the arrays to scratch memory.
+template <int NI>
+__device__ __forceinline__ uint64_t get_key(const Queue<NI> &Q, int p)
+{
+    uint64_t r = KEY_EMPTY;
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+        if (i == (p >> 6)) r = rdlane64(Q.k[i], p & 63);
+    return r;
+}
+
+template <int NI>
+__device__ __forceinline__ void mark_checked(Queue<NI> &Q, int p)
+{
+    const int s = p >> 6;
+    const uint64_t bit = 1ull << (p & 63);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) Q.chk[i] |= s == i ? bit : 0ull;
+}
+
+template <int NI>
+__device__ __forceinline__ int count_less(const Queue<NI> &Q, uint64_t key)
+{
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) c += __popcll(__ballot(Q.k[i] < key));
+    return c;
+}
+
+// Inserts an unchecked key, keeping at most L entries; returns its position, or L if it
+// falls off the end.
+template <int NI>
+__device__ __forceinline__ int insert(Queue<NI> &Q, int L, uint64_t key)
+{
+    const int pos = count_less(Q, key);
+    if (pos >= L) return L;
+    const int lane = __lane_id();
+    const int i0 = pos >> 6, pl = pos & 63;
+    uint64_t carry = KEY_EMPTY, carry_chk = 0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        if (i < i0) continue;
+        const uint64_t old = Q.k[i];
+        const uint64_t top = rdlane64(old, 63);
+        const uint64_t top_chk = Q.chk[i] >> 63;
+        const uint64_t sh = shift_up64(old, carry);
+        uint64_t nk, nc;
+        if (i == i0) {
+            nk = lane > pl ? sh : (lane == pl ? key : old);
+            const uint64_t below = low_bits(pl);
+            nc = (Q.chk[i] & below) | ((Q.chk[i] << 1) & ~below & ~(1ull << pl));
+        } else {
+            nk = sh;
+            nc = (Q.chk[i] << 1) | carry_chk;
+        }
+        const int lim = L - 64 * i;   // entries at positions >= L drop out
+        if (lim < 64) {
+            nk = lane >= lim ? KEY_EMPTY : nk;
+            nc &= low_bits(lim);
+        }
+        Q.k[i] = nk;
+        Q.chk[i] = nc;
+        carry = top;
+        carry_chk = top_chk;
+    }
+    Q.len = min(L, Q.len + 1);
+    return pos;
+}
+
+// keys of the vectors ids[0..n) to out[0..n); qs is the query, zero padded to 16 LPV floats
+template <int LPV, int PB>
+__device__ __forceinline__ void distances(const KArgs &A, const float *qs, const int32_t *ids, int n, uint64_t *out)
+{
+    constexpr int VPW = 64 / LPV;
+    const int lane = __lane_id(), grp = lane / LPV, g = lane % LPV;
+    const int nch = A.d >> 2;
+    for (int p0 = 0; p0 < n; p0 += VPW * PB) {
+        float4 x[PB][4];
+        int32_t id[PB];
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp) {
+            const int idx = p0 + pp * VPW + grp;
+            id[pp] = idx < n ? ids[idx] : -1;
+            const float *row = A.vec + (int64_t)(id[pp] < 0 ? 0 : id[pp]) * A.ld;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = g + LPV * i;
+                x[pp][i] = (id[pp] >= 0 && c < nch) ? *reinterpret_cast<const float4 *>(row + 4 * c)
+                                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float4 a = reinterpret_cast<const float4 *>(qs)[g + LPV * i], b = x[pp][i];
+                if (A.metric == SA_L2) {
+                    const double t0 = (double)a.x - (double)b.x, t1 = (double)a.y - (double)b.y;
+                    const double t2 = (double)a.z - (double)b.z, t3 = (double)a.w - (double)b.w;
+                    acc += t0 * t0; acc += t1 * t1; acc += t2 * t2; acc += t3 * t3;
+                } else {
+                    acc += (double)a.x * (double)b.x; acc += (double)a.y * (double)b.y;
+                    acc += (double)a.z * (double)b.z; acc += (double)a.w * (double)b.w;
+                }
+            }
+            acc = group_sum<LPV>(acc);
+            const int idx = p0 + pp * VPW + grp;
+            if (g == LPV - 1 && idx < n)
+                out[idx] = make_key(A.metric == SA_L2 ? (float)acc : (float)(-acc), id[pp]);
+        }
+    }
+}
+
+// find or insert u; *fresh tells whether this call inserted it.  NO_SLOT: table full.
+__device__ __forceinline__ uint32_t claim(uint32_t *T, int log2cap, uint32_t u, bool *fresh)
+{
+    const uint32_t mask = (1u << log2cap) - 1u;
+    uint32_t s = hash_slot(u, log2cap);
+    *fresh = false;
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+        const uint32_t old = atomicCAS(&T[s], 0u, u + 1u);
+        if (old == 0u) {
+            *fresh = true;
+            return s;
+        }
+        if (old == u + 1u) return s;
+        s = (s + 1) & mask;
+    }
+    return NO_SLOT;
+}
+
+template <int LPV, int NI, int PB>
+__global__ void __launch_bounds__(64) search_single(KArgs A)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    uint64_t *const nkey = reinterpret_cast<uint64_t *>(smem);    // [64] keys of new vertices
+    int32_t *const sid = reinterpret_cast<int32_t *>(nkey + 64);   // [64] their ids
+    float *const qs = reinterpret_cast<float *>(sid + 64);          // [16 LPV] the query
+
+    const int lane = __lane_id();
+    const int64_t qi = blockIdx.x;
+    const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+    const int L = A.L, R = A.R, g2 = A.glog2;
+    uint32_t *const tbl = reinterpret_cast<uint32_t *>(A.ghash) + ((size_t)qi << (g2 + 1));
+    uint32_t *const slots = tbl + (1u << g2);
+    const int cap = (3 << g2) / 4;
+
+    {
+        const int nch = A.d >> 2;
+        const float *qrow = A.queries + qi * A.ldq;
+        for (int c = lane; c < 4 * LPV; c += 64)
+            reinterpret_cast<float4 *>(qs)[c] =
+                c < nch ? *reinterpret_cast<const float4 *>(qrow + 4 * c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane == 0) sid[0] = A.entry;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    int nslot = 0, hcount = 1, nexp = 0, substeps = 0, gsteps = 0, merges = 0, flags = 0;
+    Queue<NI> Q;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        Q.k[i] = KEY_EMPTY;
+        Q.chk[i] = 0;
+    }
+    // dist(P, Q); P goes into the queue and the visited set
+    distances<LPV, PB>(A, qs, sid, 1, nkey);
+    __builtin_amdgcn_wave_barrier();
+    {
+        const uint64_t k0 = nkey[0];
+        if (lane == 0) Q.k[0] = k0;
+        Q.len = 1;
+        bool fresh = false;
+        const uint32_t s0 = lane == 0 ? claim(tbl, g2, (uint32_t)A.entry, &fresh) : 0u;
+        if (lane == 0) slots[0] = s0;
+        nslot = 1;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    const int max_sub = A.max_substeps;
+    int32_t pv = -1, pu = -1;   // vertex whose row is prefetched, and this lane's entry of it
+    int cur = 0;
+    bool stop = false;
+    while (cur < Q.len && !stop) {
+        gsteps++;
+        int sub_in_step = 0;
+        for (;;) {
+            if (substeps >= max_sub) {
+                flags |= SA_QFLAG_MAX_STEPS;
+                stop = true;
+                break;
+            }
+            substeps++;
+            sub_in_step++;
+            nexp++;
+            const int32_t v = key_id(get_key(Q, cur));
+            mark_checked(Q, cur);
+            int32_t u = v == pv ? pu : (lane < R ? A.adj[(int64_t)v * R + lane] : -1);
+            // prefetch the row of the next candidate while this step runs
+            const int nxt = first_unchecked(Q);
+            pv = -1;
+            if (nxt < Q.len) {
+                pv = key_id(get_key(Q, nxt));
+                pu = lane < R ? A.adj[(int64_t)pv * R + lane] : -1;
+            }
+            if (u < 0 || u >= A.n) u = -1;   // padding and malformed entries
+            bool fresh = false;
+            const uint32_t slot = u >= 0 ? claim(tbl, g2, (uint32_t)u, &fresh) : NO_SLOT;
+            const uint64_t fm = __ballot(fresh);
+            const int nnew = __popcll(fm);
+            if (fresh) {
+                const int r = __popcll(fm & lanemask_lt());
+                slots[nslot + r] = slot;
+                sid[r] = u;
+            }
+            nslot += nnew;
+            hcount += nnew;
+            __builtin_amdgcn_wave_barrier();
+            distances<LPV, PB>(A, qs, sid, nnew, nkey);
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t mk = lane < nnew ? nkey[lane] : KEY_EMPTY;
+            __builtin_amdgcn_wave_barrier();
+            // insert the survivors; the update position is the best place one of them takes
+            const uint64_t worst = Q.len == L ? get_key(Q, L - 1) : KEY_EMPTY;
+            uint64_t sbits = __ballot(mk < worst);
+            int U = L;
+            while (sbits) {
+                const int j = __builtin_ctzll(sbits);
+                sbits &= sbits - 1;
+                U = min(U, insert(Q, L, rdlane64(mk, j)));
+            }
+            cur = first_unchecked(Q);
+            if (hcount + R > cap) {
+                flags |= SA_QFLAG_CAPACITY;
+                stop = true;
+                break;
+            }
+            bool merge_now;
+            if (A.sync == SA_SYNC_BSP) merge_now = true;
+            else if (A.sync == SA_SYNC_STATIC) merge_now = A.static_I > 0 && sub_in_step >= A.static_I;
+            else merge_now = (double)U >= (double)L * A.rho;
+            if (cur >= Q.len || merge_now) break;
+        }
+        merges++;   // the queue is S unchanged
+    }
+
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int p = 64 * i + lane;
+        if (p < A.k) {
+            const bool ok = p < Q.len;
+            A.ids[qi * A.k + p] = ok ? key_id(Q.k[i]) : -1;
+            A.dists[qi * A.k + p] = ok ? key_dist(Q.k[i]) : __builtin_inff();
+        }
+    }
+    // leave the workspace zero-filled for the next launch
+    for (int i = lane; i < nslot; i += 64) {
+        tbl[slots[i]] = 0u;
+        slots[i] = 0u;
+    }
+    if (lane == 0 && A.stats) {
+        sa_query_stats st;
+        st.global_steps = gsteps;
+        st.substeps = substeps;
+        st.expansions = nexp;
+        st.dist_comps = hcount;
+        st.merges = merges;
+        st.flags = flags;
+        st.t_start = t_start;
+        st.t_end = __builtin_amdgcn_s_memrealtime();
+        A.stats[qi] = st;
+    }
+}
+
+template <int LPV, int NI>
+hipError_t launch1(const KArgs &A, int64_t nq, hipStream_t s)
+{
+    constexpr int PB = 1;
+    auto k = search_single<LPV, NI, PB>;
+    const uint32_t lds = 64 * 8 + 64 * 4 + 64 * LPV;
     hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64), lds, s, A);
     return hipGetLastError();
 }
 
-template <int LPV, int CPL>
-hipError_t launch1_ni(const KArgs &A, int64_t nq, uint32_t lds, hipStream_t s)
+template <int LPV>
+hipError_t launch1_ni(const KArgs &A, int64_t nq, hipStream_t s)
 {
     const int ni = (A.L + 63) / 64;
-    if (ni <= 1) return launch1<LPV, CPL, 1>(A, nq, lds, s);
-    if (ni <= 2) return launch1<LPV, CPL, 2>(A, nq, lds, s);
-    if (ni <= 4) return launch1<LPV, CPL, 4>(A, nq, lds, s);
-    if (ni <= 6) return launch1<LPV, CPL, 6>(A, nq, lds, s);
-    if (ni <= 8) return launch1<LPV, CPL, 8>(A, nq, lds, s);
-    return launch1<LPV, CPL, 16>(A, nq, lds, s);
+    if (ni <= 1) return launch1<LPV, 1>(A, nq, s);
+    if (ni <= 2) return launch1<LPV, 2>(A, nq, s);
+    if (ni <= 4) return launch1<LPV, 4>(A, nq, s);
+    if (ni <= 6) return launch1<LPV, 6>(A, nq, s);
+    if (ni <= 8) return launch1<LPV, 8>(A, nq, s);
+    return launch1<LPV, 16>(A, nq, s);
 }
 
-}  // namespace search_detail
+}  // namespace single_detail
 
-int launch_search_single(const search_detail::KArgs &A, int64_t nq, uint32_t lds, hipStream_t s)
+// lanes per vector: the smallest power of two that leaves at most four float4 chunks per lane
+static int single_lanes_per_vector(int d)
 {
-    using namespace search_detail;
-    const int nch = A.d / 4;
+    const int nch = d / 4;
+    int lpv = 1;
+    while (lpv < 64 && 4 * lpv < nch) lpv *= 2;
+    return lpv;
+}
+
+int launch_search_single(const search_detail::KArgs &A, int64_t nq, hipStream_t s)
+{
+    using namespace single_detail;
     hipError_t e;
-    if (nch <= 8) e = launch1_ni<8, 1>(A, nq, lds, s);
-    else if (nch <= 16) e = launch1_ni<16, 1>(A, nq, lds, s);
-    else if (nch <= 32) e = launch1_ni<32, 1>(A, nq, lds, s);
-    else if (nch <= 64) e = launch1_ni<64, 1>(A, nq, lds, s);
-    else if (nch <= 128) e = launch1_ni<64, 2>(A, nq, lds, s);
-    else e = launch1_ni<64, 4>(A, nq, lds, s);
+    switch (single_lanes_per_vector(A.d)) {
+    case 1: e = launch1_ni<1>(A, nq, s); break;
+    case 2: e = launch1_ni<2>(A, nq, s); break;
+    case 4: e = launch1_ni<4>(A, nq, s); break;
+    case 8: e = launch1_ni<8>(A, nq, s); break;
+    case 16: e = launch1_ni<16>(A, nq, s); break;
+    case 32: e = launch1_ni<32>(A, nq, s); break;
+    default: e = launch1_ni<64>(A, nq, s); break;
+    }
     if (e != hipSuccess) return hip_fail(e, "search kernel launch");
     return SA_OK;
 }

@@ -327,12 +327,14 @@ def test_search_edge_cases(B):
     assert (g[0][:, 1:] == -1).all() and np.isinf(g[1][:, 1:]).all()
 
 
-def test_search_visited_spill(B, sift_setup):
+@pytest.mark.parametrize("M", [1, 8])
+def test_search_visited_spill(B, sift_setup, M):
     """A tiny LDS visited table forces every query onto the workspace table; the
-    results must not change."""
+    results must not change.  With M = 1 this also runs the general kernel, which an
+    LDS table selects, instead of the single-worker one."""
     w, adj, entry = sift_setup
-    print("case: spill lds_hash_slots=1024 M=8 L=256", flush=True)
-    g, e = run_both(B, w.base, adj, entry, w.queries, 10, 256, 8, lds_hash_slots=1024)
+    print(f"case: spill lds_hash_slots=1024 M={M} L=256", flush=True)
+    g, e = run_both(B, w.base, adj, entry, w.queries, 10, 256, M, lds_hash_slots=1024)
     assert_search_equal(g, e, exact=True, label="spill")
     assert (g[2][:, 5] & 4).any()
 
@@ -344,12 +346,18 @@ def test_search_capacity_and_max_steps_flags(B, sift_setup):
     r = ix.search(dev(w.queries[:8]), 10, 256, 4, stats=True, lds_hash_slots=512, ws_hash_slots=512)
     st = host(r.stats)
     assert (st[:, 5] & 2).all()
-    print("case: max_substeps flag", flush=True)
-    r = ix.search(dev(w.queries[:8]), 10, 128, 2, stats=True, max_substeps=5)
+    print("case: capacity flag, single worker", flush=True)
+    r = ix.search(dev(w.queries[:8]), 10, 256, 1, stats=True, ws_hash_slots=512)
     st = host(r.stats)
-    assert (st[:, 5] & 1).all() and (st[:, 1] == 5).all()
-    eids, ed, _ = oracle.speedann(w.base, adj, entry, w.queries[:8], 10, 128, 2, max_substeps=5)
-    np.testing.assert_array_equal(host(r.ids), eids)
+    assert (st[:, 5] & 2).all() and (st[:, 3] <= 384).all()   # dist_comps stays under 3/4 of 512
+    for M in (1, 2):
+        print(f"case: max_substeps flag M={M}", flush=True)
+        r = ix.search(dev(w.queries[:8]), 10, 128, M, stats=True, max_substeps=5)
+        st = host(r.stats)
+        assert (st[:, 5] & 1).all() and (st[:, 1] == 5).all()
+        eids, ed, est = oracle.speedann(w.base, adj, entry, w.queries[:8], 10, 128, M, max_substeps=5)
+        np.testing.assert_array_equal(host(r.ids), eids)
+        np.testing.assert_array_equal(host(r.dists), ed)
 
 
 def test_search_ip_deep_shaped(B):
