@@ -168,8 +168,11 @@ __device__ __forceinline__ int insert(Queue<NI> &Q, int L, uint64_t key)
     return pos;
 }
 
-// keys of the vectors ids[0..n) to out[0..n); qs is the query, zero padded to 16 LPV floats
-template <int LPV, int PB>
+// Keys of the vectors ids[0..n) to out[0..n); qs is the query, zero padded to 16 LPV
+// floats.  Every load is issued unconditionally (from a clamped address, its value
+// dropped afterwards): loads under a lane condition each get their own wait, which would
+// turn one memory round trip into four.
+template <int LPV, int PB, bool L2>
 __device__ __forceinline__ void distances(const KArgs &A, const float *qs, const int32_t *ids, int n, uint64_t *out)
 {
     constexpr int VPW = 64 / LPV;
@@ -181,13 +184,13 @@ __device__ __forceinline__ void distances(const KArgs &A, const float *qs, const
 #pragma unroll
         for (int pp = 0; pp < PB; ++pp) {
             const int idx = p0 + pp * VPW + grp;
-            id[pp] = idx < n ? ids[idx] : -1;
+            const int32_t raw = ids[idx & 63];
+            id[pp] = idx < n ? raw : -1;
             const float *row = A.vec + (int64_t)(id[pp] < 0 ? 0 : id[pp]) * A.ld;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int c = g + LPV * i;
-                x[pp][i] = (id[pp] >= 0 && c < nch) ? *reinterpret_cast<const float4 *>(row + 4 * c)
-                                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+                x[pp][i] = *reinterpret_cast<const float4 *>(row + 4 * (c < nch ? c : 0));
             }
         }
 #pragma unroll
@@ -195,20 +198,22 @@ __device__ __forceinline__ void distances(const KArgs &A, const float *qs, const
             double acc = 0.0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float4 a = reinterpret_cast<const float4 *>(qs)[g + LPV * i], b = x[pp][i];
-                if (A.metric == SA_L2) {
-                    const double t0 = (double)a.x - (double)b.x, t1 = (double)a.y - (double)b.y;
-                    const double t2 = (double)a.z - (double)b.z, t3 = (double)a.w - (double)b.w;
+                const bool in = g + LPV * i < nch;
+                const float4 a = reinterpret_cast<const float4 *>(qs)[g + LPV * i];
+                const float bx = in ? x[pp][i].x : 0.f, by = in ? x[pp][i].y : 0.f;
+                const float bz = in ? x[pp][i].z : 0.f, bw = in ? x[pp][i].w : 0.f;
+                if constexpr (L2) {
+                    const double t0 = (double)a.x - (double)bx, t1 = (double)a.y - (double)by;
+                    const double t2 = (double)a.z - (double)bz, t3 = (double)a.w - (double)bw;
                     acc += t0 * t0; acc += t1 * t1; acc += t2 * t2; acc += t3 * t3;
                 } else {
-                    acc += (double)a.x * (double)b.x; acc += (double)a.y * (double)b.y;
-                    acc += (double)a.z * (double)b.z; acc += (double)a.w * (double)b.w;
+                    acc += (double)a.x * (double)bx; acc += (double)a.y * (double)by;
+                    acc += (double)a.z * (double)bz; acc += (double)a.w * (double)bw;
                 }
             }
             acc = group_sum<LPV>(acc);
             const int idx = p0 + pp * VPW + grp;
-            if (g == LPV - 1 && idx < n)
-                out[idx] = make_key(A.metric == SA_L2 ? (float)acc : (float)(-acc), id[pp]);
+            if (g == LPV - 1 && idx < n) out[idx] = make_key(L2 ? (float)acc : (float)(-acc), id[pp]);
         }
     }
 }
@@ -231,7 +236,7 @@ __device__ __forceinline__ uint32_t claim(uint32_t *T, int log2cap, uint32_t u, 
     return NO_SLOT;
 }
 
-template <int LPV, int NI, int PB>
+template <int LPV, int NI, int PB, bool L2>
 __global__ void __launch_bounds__(64) search_single(KArgs A)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -257,7 +262,10 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
     }
     __builtin_amdgcn_wave_barrier();
 
-    int nslot = 0, hcount = 1, nexp = 0, substeps = 0, gsteps = 0, merges = 0, flags = 0;
+    // one worker: every local step expands one vertex, and every visited vertex has one
+    // table slot, so the step count is the expansion count and the slot count is the
+    // distance count
+    int nslot = 0, substeps = 0, gsteps = 0, merges = 0, flags = 0;
     Queue<NI> Q;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
@@ -265,7 +273,7 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
         Q.chk[i] = 0;
     }
     // dist(P, Q); P goes into the queue and the visited set
-    distances<LPV, PB>(A, qs, sid, 1, nkey);
+    distances<LPV, PB, L2>(A, qs, sid, 1, nkey);
     __builtin_amdgcn_wave_barrier();
     {
         const uint64_t k0 = nkey[0];
@@ -279,6 +287,9 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
     __builtin_amdgcn_wave_barrier();
 
     const int max_sub = A.max_substeps;
+    const int32_t n = (int32_t)A.n;
+    // this lane's entry of an adjacency row (R <= 64); lanes past R load entry 0 and drop it
+    const int32_t *const adj_lane = A.adj + (lane < R ? lane : 0);
     int32_t pv = -1, pu = -1;   // vertex whose row is prefetched, and this lane's entry of it
     int cur = 0;
     bool stop = false;
@@ -293,18 +304,15 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
             }
             substeps++;
             sub_in_step++;
-            nexp++;
             const int32_t v = key_id(get_key(Q, cur));
             mark_checked(Q, cur);
-            int32_t u = v == pv ? pu : (lane < R ? A.adj[(int64_t)v * R + lane] : -1);
+            int32_t u = pu;
+            if (v != pv) u = adj_lane[(int64_t)v * R];
             // prefetch the row of the next candidate while this step runs
             const int nxt = first_unchecked(Q);
-            pv = -1;
-            if (nxt < Q.len) {
-                pv = key_id(get_key(Q, nxt));
-                pu = lane < R ? A.adj[(int64_t)pv * R + lane] : -1;
-            }
-            if (u < 0 || u >= A.n) u = -1;   // padding and malformed entries
+            pv = nxt < Q.len ? key_id(get_key(Q, nxt)) : v;
+            pu = adj_lane[(int64_t)pv * R];
+            if (lane >= R || u < 0 || u >= n) u = -1;   // padding and malformed entries
             bool fresh = false;
             const uint32_t slot = u >= 0 ? claim(tbl, g2, (uint32_t)u, &fresh) : NO_SLOT;
             const uint64_t fm = __ballot(fresh);
@@ -315,9 +323,8 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
                 sid[r] = u;
             }
             nslot += nnew;
-            hcount += nnew;
             __builtin_amdgcn_wave_barrier();
-            distances<LPV, PB>(A, qs, sid, nnew, nkey);
+            distances<LPV, PB, L2>(A, qs, sid, nnew, nkey);
             __builtin_amdgcn_wave_barrier();
             const uint64_t mk = lane < nnew ? nkey[lane] : KEY_EMPTY;
             __builtin_amdgcn_wave_barrier();
@@ -331,7 +338,7 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
                 U = min(U, insert(Q, L, rdlane64(mk, j)));
             }
             cur = first_unchecked(Q);
-            if (hcount + R > cap) {
+            if (nslot + R > cap) {
                 flags |= SA_QFLAG_CAPACITY;
                 stop = true;
                 break;
@@ -363,8 +370,8 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
         sa_query_stats st;
         st.global_steps = gsteps;
         st.substeps = substeps;
-        st.expansions = nexp;
-        st.dist_comps = hcount;
+        st.expansions = substeps;
+        st.dist_comps = nslot;
         st.merges = merges;
         st.flags = flags;
         st.t_start = t_start;
@@ -377,7 +384,7 @@ template <int LPV, int NI>
 hipError_t launch1(const KArgs &A, int64_t nq, hipStream_t s)
 {
     constexpr int PB = 1;
-    auto k = search_single<LPV, NI, PB>;
+    auto k = A.metric == SA_L2 ? search_single<LPV, NI, PB, true> : search_single<LPV, NI, PB, false>;
     const uint32_t lds = 64 * 8 + 64 * 4 + 64 * LPV;
     hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64), lds, s, A);
     return hipGetLastError();
