@@ -236,11 +236,13 @@ class Index:
                                      adj.data_ptr(), adj.shape[1], self.entry, C.byref(h)), "sa_index_create")
         self._h = h
         self._ws = None
+        self._lib = lib()   # kept for __del__, which may run after module teardown
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().sa_index_destroy(h)
+        L = getattr(self, "_lib", None)
+        if h is not None and h.value and L is not None:
+            L.sa_index_destroy(h)
             self._h = None
 
     def workspace_bytes(self, nq, k, L, M, params: SearchParams) -> int:

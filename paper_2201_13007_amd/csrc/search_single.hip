@@ -10,8 +10,8 @@
 // Queue.  NI = ceil(L / 64) slots per lane hold the sorted 64-bit keys (order-preserving
 // distance bits, id); entry p sits in slot p / 64 of lane p % 64.  The CHECKED flags are
 // wave-uniform 64-bit masks, one per slot, so finding the first unchecked entry is scalar
-// work.  An insertion moves every entry at or after the insertion point up by one lane
-// with a DPP wavefront shift, carrying lane 63 into lane 0 of the next slot.
+// work.  The new entries of a step are merged in one pass: each destination computes how
+// many of them land below it and pulls its old entry with a cross-lane permute.
 //
 // Visited set.  Open addressing over 32-bit entries (id + 1; zero is empty) in the
 // query's workspace region, claimed with compare-and-swap.  The slots a query fills are
@@ -32,7 +32,6 @@ using search_detail::lanemask_lt;
 using search_detail::rdlane64;
 
 constexpr int DPP_ROW_SHR = 0x110;     // + n: row_shr:n
-constexpr int DPP_WAVE_SHR1 = 0x138;   // wave_shr:1
 constexpr int DPP_ROW_BCAST15 = 0x142;
 constexpr int DPP_ROW_BCAST31 = 0x143;
 
@@ -63,14 +62,6 @@ __device__ __forceinline__ double group_sum(double v)
     if constexpr (LPV >= 32) v += dpp_f64<DPP_ROW_BCAST15, 0xA>(v);
     if constexpr (LPV >= 64) v += dpp_f64<DPP_ROW_BCAST31, 0xC>(v);
     return v;
-}
-
-// lane l gets lane l - 1 of v; lane 0 gets carry
-__device__ __forceinline__ uint64_t shift_up64(uint64_t v, uint64_t carry)
-{
-    const uint32_t lo = dpp32<DPP_WAVE_SHR1>((uint32_t)v, (uint32_t)carry);
-    const uint32_t hi = dpp32<DPP_WAVE_SHR1>((uint32_t)(v >> 32), (uint32_t)(carry >> 32));
-    return ((uint64_t)hi << 32) | lo;
 }
 
 // bits [0, n) set, n in [0, 64]
@@ -128,44 +119,75 @@ __device__ __forceinline__ int count_less(const Queue<NI> &Q, uint64_t key)
     return c;
 }
 
-// Inserts an unchecked key, keeping at most L entries; returns its position, or L if it
-// falls off the end.
-template <int NI>
-__device__ __forceinline__ int insert(Queue<NI> &Q, int L, uint64_t key)
+__device__ __forceinline__ uint64_t bpermute64(int addr, uint64_t v)
 {
-    const int pos = count_less(Q, key);
-    if (pos >= L) return L;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inserts the unchecked keys mk of the lanes in sbits (distinct, none in the queue),
+// keeping at most L entries, and returns the update position: the best position one of
+// them takes (L if none stays).  One pass for the whole batch: the key of rank r among
+// them lands at f = (queue keys below it) + r; the landing positions form a bit mask per
+// slot, and every other destination P takes the old entry at P - c(P), c(P) the number
+// of landings below P, which lies in P's slot or the one before at lane (P - c(P)) mod
+// 64.  stage (LDS, 64 keys) receives the batch sorted by rank.
+template <int NI>
+__device__ __forceinline__ int insert_batch(Queue<NI> &Q, int L, uint64_t mk, uint64_t sbits, uint64_t *stage)
+{
     const int lane = __lane_id();
-    const int i0 = pos >> 6, pl = pos & 63;
-    uint64_t carry = KEY_EMPTY, carry_chk = 0;
+    const bool surv = (sbits >> lane) & 1ull;
+    uint64_t land[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) land[i] = 0;
+    int fmin = L;
+    for (uint64_t b = sbits; b; b &= b - 1) {
+        const int j = __builtin_ctzll(b);
+        const uint64_t kj = rdlane64(mk, j);
+        const int r = __popcll(__ballot(surv && mk < kj));
+        const int f = count_less(Q, kj) + r;
+        if (lane == 0) stage[r] = kj;
+        fmin = min(fmin, f);
+        const uint64_t bit = f < L ? 1ull << (f & 63) : 0ull;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) land[i] |= (f >> 6) == i ? bit : 0ull;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (fmin >= L) return L;
+    const int nlen = min(L, Q.len + __popcll(sbits));
+    const int i_first = fmin >> 6;
+    int below = 0;   // landings in the slots under slot i
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+        if (i < i_first) below += __popcll(land[i]);
+    int base[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        if (i < i0) continue;
-        const uint64_t old = Q.k[i];
-        const uint64_t top = rdlane64(old, 63);
-        const uint64_t top_chk = Q.chk[i] >> 63;
-        const uint64_t sh = shift_up64(old, carry);
-        uint64_t nk, nc;
-        if (i == i0) {
-            nk = lane > pl ? sh : (lane == pl ? key : old);
-            const uint64_t below = low_bits(pl);
-            nc = (Q.chk[i] & below) | ((Q.chk[i] << 1) & ~below & ~(1ull << pl));
-        } else {
-            nk = sh;
-            nc = (Q.chk[i] << 1) | carry_chk;
-        }
-        const int lim = L - 64 * i;   // entries at positions >= L drop out
-        if (lim < 64) {
-            nk = lane >= lim ? KEY_EMPTY : nk;
-            nc &= low_bits(lim);
-        }
-        Q.k[i] = nk;
-        Q.chk[i] = nc;
-        carry = top;
-        carry_chk = top_chk;
+        base[i] = below;
+        if (i >= i_first) below += __popcll(land[i]);
     }
-    Q.len = min(L, Q.len + 1);
-    return pos;
+#pragma unroll
+    for (int i = NI - 1; i >= 0; --i) {
+        if (i < i_first) continue;
+        const int c = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(land[i] >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)land[i], (uint32_t)base[i]));
+        const bool lands = (land[i] >> lane) & 1ull;
+        const int src = (lane - c) & 63;
+        const int addr = src << 2;
+        const bool from_prev = lane < c;
+        const uint64_t cur = bpermute64(addr, Q.k[i]);
+        const uint64_t prv = i > 0 ? bpermute64(addr, Q.k[i > 0 ? i - 1 : 0]) : KEY_EMPTY;
+        const uint64_t prv_chk = i > 0 ? Q.chk[i > 0 ? i - 1 : 0] : 0ull;
+        const uint64_t sk = stage[c & 63];
+        const int P = 64 * i + lane;
+        const uint64_t ob = ((from_prev ? prv_chk : Q.chk[i]) >> src) & 1ull;
+        const bool keep = P < nlen;
+        Q.k[i] = keep ? (lands ? sk : (from_prev ? prv : cur)) : KEY_EMPTY;
+        Q.chk[i] = __ballot(keep && !lands && ob);
+    }
+    Q.len = nlen;
+    return fmin;
 }
 
 // Keys of the vectors ids[0..n) to out[0..n); qs is the query, zero padded to 16 LPV
@@ -330,13 +352,8 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
             __builtin_amdgcn_wave_barrier();
             // insert the survivors; the update position is the best place one of them takes
             const uint64_t worst = Q.len == L ? get_key(Q, L - 1) : KEY_EMPTY;
-            uint64_t sbits = __ballot(mk < worst);
-            int U = L;
-            while (sbits) {
-                const int j = __builtin_ctzll(sbits);
-                sbits &= sbits - 1;
-                U = min(U, insert(Q, L, rdlane64(mk, j)));
-            }
+            const uint64_t sbits = __ballot(mk < worst);
+            const int U = sbits ? insert_batch(Q, L, mk, sbits, nkey) : L;
             cur = first_unchecked(Q);
             if (nslot + R > cap) {
                 flags |= SA_QFLAG_CAPACITY;
