@@ -10,13 +10,14 @@ using search_detail::Ctrl;
 using search_detail::KArgs;
 
 struct Layout {
-    uint32_t o_skey, o_srank, o_schk, o_lskey, o_lsmeta, o_newkey, o_claim, o_ctrl, o_hash, total;
+    uint32_t o_skey, o_srank, o_schk, o_lskey, o_lsmeta, o_newkey, o_claim, o_ctrl, o_hash, o_q, total;
 };
 
 uint32_t align_up(uint32_t x, uint32_t a) { return (x + a - 1) / a * a; }
 
-// S, the rank array and the LDS copies of the local queues exist only with M >= 2
-Layout make_layout(int L, int M, int llog2)
+// S, the rank array and the LDS copies of the local queues exist only with M >= 2; the
+// query takes 16 floats per lane of a vector group
+Layout make_layout(int L, int M, int llog2, int lpv)
 {
     Layout Y;
     const uint32_t LL = M >= 2 ? (uint32_t)L : 0u;
@@ -31,6 +32,7 @@ Layout make_layout(int L, int M, int llog2)
     Y.o_claim = o; o += 4u * 64u * M;
     Y.o_ctrl = o; o += align_up(sizeof(Ctrl), 16);
     Y.o_hash = o; o += llog2 > 0 ? (8u << llog2) : 0u;
+    Y.o_q = o; o += 64u * (uint32_t)lpv;
     Y.total = o;
     return Y;
 }
@@ -93,7 +95,7 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
         return set_error(SA_ECAPACITY, "workspace of %zu bytes is smaller than the %zu bytes needed", a.ws_bytes, need);
     if (a.workspace == nullptr && need > 0) return set_error(SA_EINVAL, "workspace is NULL");
     if (((uintptr_t)a.workspace & 255u) != 0) return set_error(SA_EINVAL, "workspace must be 256-byte aligned");
-    Layout Y = make_layout(a.L, a.M, llog2);
+    Layout Y = make_layout(a.L, a.M, llog2, search_detail::lanes_per_vector(a.d));
     if (Y.total > 160u * 1024u)
         return set_error(SA_ECAPACITY, "L=%d, M=%d need %u bytes of LDS per query (limit 163840); lower L, M or "
                          "lds_hash_slots", a.L, a.M, Y.total);
@@ -107,7 +109,7 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     A.rho = a.p.rho; A.glog2 = glog2; A.llog2 = llog2;
     A.o_skey = Y.o_skey; A.o_srank = Y.o_srank; A.o_schk = Y.o_schk; A.o_lskey = Y.o_lskey;
     A.o_lsmeta = Y.o_lsmeta; A.o_newkey = Y.o_newkey; A.o_claim = Y.o_claim; A.o_ctrl = Y.o_ctrl;
-    A.o_hash = Y.o_hash;
+    A.o_hash = Y.o_hash; A.o_q = Y.o_q;
     if (a.nq == 0) return SA_OK;
     if (a.d > 1024) return set_error(SA_EUNSUPPORTED, "d=%d exceeds 1024", a.d);
     if (compact_table(a.M, llog2)) return launch_search_single(A, a.nq, stream);

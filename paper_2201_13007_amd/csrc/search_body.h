@@ -7,9 +7,14 @@
 // NI = ceil(L / 64) slots per lane hold the sorted 64-bit keys (distance bits, id) and a
 // 32-bit tag each, entry p in slot p / 64 of lane p % 64.  The tag holds the index of
 // the S entry it was copied from (0xFFFF for vertices the worker inserted itself), MINE
-// (the worker may expand it) and CHECKED.  Finding the first candidate to expand,
-// counting smaller keys and inserting (a shift by one lane) are ballots and cross-lane
-// moves: no memory round trip.
+// (the worker may expand it) and CHECKED.  Finding the first candidate to expand and
+// counting smaller keys are ballots; a local step's new entries are merged in one pass
+// of cross-lane permutes.  No memory round trip.
+//
+// Distances: LPV lanes share one vector, each lane four float4 chunks, accumulated in
+// double precision, summed by DPP row shifts and rounded once to float; the query sits
+// in LDS for all workers.  Every gather and row load is issued unconditionally (from a
+// clamped address): loads under lane conditions each get their own wait.
 //
 // Global steps with one active worker (every step when M = 1; the first step of a
 // staged search) run on wavefront 0 alone, with no barrier: the merge of a single local
@@ -68,7 +73,7 @@ struct KArgs {
     int32_t d, metric, R, entry, k, L, M, sync, static_I, staged, max_substeps;
     double rho;
     int32_t glog2, llog2;        // llog2 == 0: no LDS table
-    uint32_t o_skey, o_srank, o_schk, o_lskey, o_lsmeta, o_newkey, o_claim, o_ctrl, o_hash;
+    uint32_t o_skey, o_srank, o_schk, o_lskey, o_lsmeta, o_newkey, o_claim, o_ctrl, o_hash, o_q;
 };
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
@@ -83,22 +88,6 @@ __device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l)
 {
     return ((uint64_t)rdlane((uint32_t)(v >> 32), l) << 32) | rdlane((uint32_t)v, l);
 }
-__device__ __forceinline__ uint64_t shfl_up64(uint64_t v)
-{
-    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, 1, 64);
-    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), 1, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-__device__ __forceinline__ uint64_t wave_min64(uint64_t v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        uint64_t o = (uint64_t)__shfl_xor((unsigned long long)v, off, 64);
-        v = o < v ? o : v;
-    }
-    return v;
-}
-
 // Phase one of a claim: find or insert u, leaving the smallest tag of this local step
 // in its slot.  Returns the slot, or NO_SLOT if the table is full; *fresh tells whether
 // this call inserted u.
@@ -139,6 +128,115 @@ __device__ __forceinline__ int lower_bound(const uint64_t *a, int n, uint64_t ke
         else hi = mid;
     }
     return lo;
+}
+
+// ---------------------------------------------------------------- cross-lane helpers
+
+constexpr int DPP_ROW_SHR = 0x110;     // + n: row_shr:n
+constexpr int DPP_ROW_BCAST15 = 0x142;
+constexpr int DPP_ROW_BCAST31 = 0x143;
+
+// lanes whose DPP source is invalid (outside the row or the enabled rows) keep `old`
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v, uint32_t old)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWMASK, 0xF, false);
+}
+
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = dpp32<CTRL, ROWMASK>((uint32_t)b, 0u);
+    const uint32_t hi = dpp32<CTRL, ROWMASK>((uint32_t)(b >> 32), 0u);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// sum of each group of LPV lanes, left in the group's last lane
+template <int LPV>
+__device__ __forceinline__ double group_sum(double v)
+{
+    if constexpr (LPV >= 2) v += dpp_f64<DPP_ROW_SHR + 1>(v);
+    if constexpr (LPV >= 4) v += dpp_f64<DPP_ROW_SHR + 2>(v);
+    if constexpr (LPV >= 8) v += dpp_f64<DPP_ROW_SHR + 4>(v);
+    if constexpr (LPV >= 16) v += dpp_f64<DPP_ROW_SHR + 8>(v);
+    if constexpr (LPV >= 32) v += dpp_f64<DPP_ROW_BCAST15, 0xA>(v);
+    if constexpr (LPV >= 64) v += dpp_f64<DPP_ROW_BCAST31, 0xC>(v);
+    return v;
+}
+
+// bits [0, n) set, n in [0, 64]
+__device__ __forceinline__ uint64_t low_bits(int n)
+{
+    return n <= 0 ? 0ull : (n >= 64 ? ~0ull : (~0ull >> (64 - n)));
+}
+
+__device__ __forceinline__ uint64_t bpermute64(int addr, uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// lanes per vector: the smallest power of two that leaves at most four float4 chunks per
+// lane (d <= 1024)
+__host__ __device__ inline int lanes_per_vector(int d)
+{
+    const int nch = d / 4;
+    int lpv = 1;
+    while (lpv < 64 && 4 * lpv < nch) lpv *= 2;
+    return lpv;
+}
+
+// Keys of the vectors ids[0..n) to out[0..n); qs is the query, zero padded to 16 LPV
+// floats.  Every load is issued unconditionally (from a clamped address, its value
+// dropped afterwards): loads under a lane condition each get their own wait, which would
+// turn one memory round trip into four.
+template <int LPV, bool L2>
+__device__ __forceinline__ void distances(const KArgs &A, const float *qs, const int32_t *ids, int n, uint64_t *out)
+{
+    constexpr int VPW = 64 / LPV;
+    const int lane = __lane_id(), grp = lane / LPV, g = lane % LPV;
+    const int nch = A.d >> 2;
+    constexpr int PB = 1;   // more vectors in flight cost two registers each (d = 128)
+    for (int p0 = 0; p0 < n; p0 += VPW * PB) {
+        float4 x[PB][4];
+        int32_t id[PB];
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp) {
+            const int idx = p0 + pp * VPW + grp;
+            const int32_t raw = ids[idx & 63];
+            id[pp] = idx < n ? raw : -1;
+            const float *row = A.vec + (int64_t)(id[pp] < 0 ? 0 : id[pp]) * A.ld;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = g + LPV * i;
+                x[pp][i] = *reinterpret_cast<const float4 *>(row + 4 * (c < nch ? c : 0));
+            }
+        }
+#pragma unroll
+        for (int pp = 0; pp < PB; ++pp) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool in = g + LPV * i < nch;
+                const float4 a = reinterpret_cast<const float4 *>(qs)[g + LPV * i];
+                const float bx = in ? x[pp][i].x : 0.f, by = in ? x[pp][i].y : 0.f;
+                const float bz = in ? x[pp][i].z : 0.f, bw = in ? x[pp][i].w : 0.f;
+                if constexpr (L2) {
+                    const double t0 = (double)a.x - (double)bx, t1 = (double)a.y - (double)by;
+                    const double t2 = (double)a.z - (double)bz, t3 = (double)a.w - (double)bw;
+                    acc += t0 * t0; acc += t1 * t1; acc += t2 * t2; acc += t3 * t3;
+                } else {
+                    acc += (double)a.x * (double)bx; acc += (double)a.y * (double)by;
+                    acc += (double)a.z * (double)bz; acc += (double)a.w * (double)bw;
+                }
+            }
+            acc = group_sum<LPV>(acc);
+            const int idx = p0 + pp * VPW + grp;
+            if (g == LPV - 1 && idx < n) out[idx] = make_key(L2 ? (float)acc : (float)(-acc), id[pp]);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- register queue
@@ -204,96 +302,66 @@ __device__ __forceinline__ void rl_or_meta(RList<NI> &l, int p, uint32_t bits)
         if (ii == i && __lane_id() == ln) l.m[ii] |= bits;
 }
 
-// insert one entry, keeping the queue sorted and at most L long
+// Inserts the keys mk of the lanes in sbits (distinct, none in the queue) as the worker's
+// own unchecked entries, keeping at most L of the len + |sbits| entries; returns the
+// update position: the best position one of them takes (L if none stays).  One pass for
+// the whole batch: the key of rank r among them lands at f = (queue keys below it) + r;
+// the landing positions form a bit mask per slot, and every other destination P takes the
+// entry at P - c(P), c(P) the number of landings below P, which lies in P's slot or the
+// one before at lane (P - c(P)) mod 64.  stage (LDS, 64 keys) receives the batch by rank.
 template <int NI>
-__device__ __forceinline__ void rl_insert(RList<NI> &l, int L, uint64_t key, uint32_t meta)
+__device__ __forceinline__ int rl_insert_batch(RList<NI> &l, int L, int len, uint64_t mk, uint64_t sbits,
+                                               uint64_t *stage)
 {
-    const int pos = rl_count_less(l, key);
-    if (pos >= L) return;
     const int lane = __lane_id();
-    uint64_t ck = KEY_EMPTY;
-    uint32_t cm = 0;
+    const bool surv = (sbits >> lane) & 1ull;
+    uint64_t land[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) land[i] = 0;
+    int fmin = L;
+    for (uint64_t b = sbits; b; b &= b - 1) {
+        const int j = __builtin_ctzll(b);
+        const uint64_t kj = rdlane64(mk, j);
+        const int r = __popcll(__ballot(surv && mk < kj));
+        const int f = rl_count_less(l, kj) + r;
+        if (lane == 0) stage[r] = kj;
+        fmin = min(fmin, f);
+        const uint64_t bit = f < L ? 1ull << (f & 63) : 0ull;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) land[i] |= (f >> 6) == i ? bit : 0ull;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (fmin >= L) return L;
+    const int nlen = min(L, len + __popcll(sbits));
+    const int i_first = fmin >> 6;
+    int below = 0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+        if (i < i_first) below += __popcll(land[i]);
+    int base[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        if ((i + 1) * 64 <= pos) continue;   // slot entirely before the insertion point
-        const int p = i * 64 + lane;
-        uint64_t pk = shfl_up64(l.k[i]);
-        uint32_t pm = (uint32_t)__shfl_up((int)l.m[i], 1, 64);
-        const uint64_t topk = rdlane64(l.k[i], 63);
-        const uint32_t topm = rdlane(l.m[i], 63);
-        if (lane == 0) {
-            pk = ck;
-            pm = cm;
-        }
-        uint64_t nk = p > pos ? pk : (p == pos ? key : l.k[i]);
-        uint32_t nm = p > pos ? pm : (p == pos ? meta : l.m[i]);
-        if (p >= L) {
-            nk = KEY_EMPTY;
-            nm = 0;
-        }
-        l.k[i] = nk;
-        l.m[i] = nm;
-        ck = topk;
-        cm = topm;
+        base[i] = below;
+        if (i >= i_first) below += __popcll(land[i]);
     }
-}
-
-// Distances from the query (q chunks in registers) to the vectors listed in ids[0..n),
-// written as keys to out[0..n).  LPV lanes share one vector (float4 chunks c = g,
-// g + LPV, ...); every lane accumulates its chunks in double precision, the group sums
-// its lanes with a butterfly and the group's first lane rounds the sum once to float.
-template <int LPV, int CPL>
-__device__ void wave_distances(const KArgs &A, const float4 (&q)[CPL], const int32_t *ids, int n, uint64_t *out)
-{
-    constexpr int VPW = 64 / LPV;
-    constexpr int PB = CPL >= 4 ? 1 : 4 / CPL;
-    const int lane = __lane_id();
-    const int grp = lane / LPV, g = lane % LPV;
-    const int nch = A.d >> 2;
-    const int npass = (n + VPW - 1) / VPW;
-    for (int p0 = 0; p0 < npass; p0 += PB) {
-        float4 xv[PB][CPL];
 #pragma unroll
-        for (int pp = 0; pp < PB; ++pp) {
-            int idx = (p0 + pp) * VPW + grp;
-            if (idx < n) {
-                const float *row = A.vec + (int64_t)ids[idx] * A.ld;
-#pragma unroll
-                for (int i = 0; i < CPL; ++i) {
-                    int c = g + LPV * i;
-                    if (c < nch) xv[pp][i] = *reinterpret_cast<const float4 *>(row + 4 * c);
-                }
-            }
-        }
-#pragma unroll
-        for (int pp = 0; pp < PB; ++pp) {
-            int idx = (p0 + pp) * VPW + grp;
-            double acc = 0.0;
-            if (idx < n) {
-#pragma unroll
-                for (int i = 0; i < CPL; ++i) {
-                    int c = g + LPV * i;
-                    if (c < nch) {
-                        const float4 a = q[i], b = xv[pp][i];
-                        if (A.metric == SA_L2) {
-                            double t0 = (double)a.x - (double)b.x, t1 = (double)a.y - (double)b.y;
-                            double t2 = (double)a.z - (double)b.z, t3 = (double)a.w - (double)b.w;
-                            acc += t0 * t0; acc += t1 * t1; acc += t2 * t2; acc += t3 * t3;
-                        } else {
-                            acc += (double)a.x * (double)b.x; acc += (double)a.y * (double)b.y;
-                            acc += (double)a.z * (double)b.z; acc += (double)a.w * (double)b.w;
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int off = LPV / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            if (g == 0 && idx < n) {
-                float dist = A.metric == SA_L2 ? (float)acc : (float)(-acc);
-                out[idx] = make_key(dist, ids[idx]);
-            }
-        }
+    for (int i = NI - 1; i >= 0; --i) {
+        if (i < i_first) continue;
+        const int c = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(land[i] >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)land[i], (uint32_t)base[i]));
+        const bool lands = (land[i] >> lane) & 1ull;
+        const int addr = ((lane - c) & 63) << 2;
+        const bool from_prev = lane < c;
+        const uint64_t ck = bpermute64(addr, l.k[i]);
+        const uint32_t cm = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)l.m[i]);
+        const uint64_t pk = i > 0 ? bpermute64(addr, l.k[i > 0 ? i - 1 : 0]) : KEY_EMPTY;
+        const uint32_t pm = i > 0 ? (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)l.m[i > 0 ? i - 1 : 0]) : 0u;
+        const uint64_t sk = stage[c & 63];
+        const bool keep = 64 * i + lane < nlen;
+        l.k[i] = keep ? (lands ? sk : (from_prev ? pk : ck)) : KEY_EMPTY;
+        l.m[i] = keep ? (lands ? (META_SIDX | META_MINE) : (from_prev ? pm : cm)) : 0u;
     }
+    return fmin;
 }
 
 // Records workspace slots written by fresh claims of this wave (prefix over the wave,
@@ -329,7 +397,7 @@ __device__ void migrate_table(const unsigned long long *lh, int llog2, unsigned 
     }
 }
 
-template <int LPV, int CPL, int NI, bool MULTI>
+template <int LPV, int NI>
 __device__ __forceinline__ void search_body(const KArgs &A)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -367,16 +435,19 @@ __device__ __forceinline__ void search_body(const KArgs &A)
         C->gsteps = C->substeps = C->merges = 0;
         C->epoch = 1;
     }
-    float4 q[CPL];
+    // the query, zero padded to 16 LPV floats, shared by the workers
+    float *const qs = reinterpret_cast<float *>(smem + A.o_q);
     {
         const float *qrow = A.queries + qi * A.ldq;
-        const int g = lane % LPV, nch = A.d >> 2;
-#pragma unroll
-        for (int i = 0; i < CPL; ++i) {
-            int c = g + LPV * i;
-            q[i] = c < nch ? *reinterpret_cast<const float4 *>(qrow + 4 * c) : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+        const int nch = A.d >> 2;
+        for (int c = tid; c < 4 * LPV; c += nthr)
+            reinterpret_cast<float4 *>(qs)[c] =
+                c < nch ? *reinterpret_cast<const float4 *>(qrow + 4 * c) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    const bool l2 = A.metric == SA_L2;
+    const int32_t n = (int32_t)A.n;
+    // this lane's entry of an adjacency row (R <= 64); lanes past R load entry 0 and drop it
+    const int32_t *const adj_lane = A.adj + (lane < R ? lane : 0);
     __syncthreads();
 
     RList<NI> ls;
@@ -389,7 +460,8 @@ __device__ __forceinline__ void search_body(const KArgs &A)
     if (w == 0) {
         if (lane == 0) claim[0] = A.entry;
         __builtin_amdgcn_wave_barrier();
-        wave_distances<LPV, CPL>(A, q, claim, 1, nkey);
+        if (l2) distances<LPV, true>(A, qs, claim, 1, nkey);
+        else distances<LPV, false>(A, qs, claim, 1, nkey);
         __builtin_amdgcn_wave_barrier();
         const uint64_t k0 = nkey[0];
         bool fresh = false;
@@ -442,20 +514,18 @@ __device__ __forceinline__ void search_body(const KArgs &A)
                     rl_or_meta(ls, cur, META_CHK);
                     nexp++;
                     const int32_t v = key_id(vkey);
-                    int32_t u;
-                    if (v == pv) u = pu;
-                    else u = lane < R ? A.adj[(int64_t)v * R + lane] : -1;
+                    int32_t u = pu;
+                    if (v != pv) u = adj_lane[(int64_t)v * R];
                     // prefetch the row of the next candidate while this step runs
                     const int nxt = rl_first_expandable(ls);
-                    pv = -1;
-                    if (nxt < len) {
-                        uint64_t nk;
+                    {
+                        uint64_t nk = vkey;
                         uint32_t nm;
-                        rl_get(ls, nxt, nk, nm);
+                        if (nxt < len) rl_get(ls, nxt, nk, nm);
                         pv = key_id(nk);
-                        pu = lane < R ? A.adj[(int64_t)pv * R + lane] : -1;
+                        pu = adj_lane[(int64_t)pv * R];
                     }
-                    if (u >= A.n) u = -1;   // malformed row entries are ignored like padding
+                    if (lane >= R || u < 0 || u >= n) u = -1;   // padding and malformed entries
                     bool fresh = false;
                     uint32_t slot = NO_SLOT;
                     const uint32_t tag = (epoch << 10) | (uint32_t)lane;
@@ -467,7 +537,8 @@ __device__ __forceinline__ void search_body(const KArgs &A)
                     hcount += nclaim;
                     if (fresh) claim[__popcll(cm & lanemask_lt())] = u;
                     __builtin_amdgcn_wave_barrier();
-                    wave_distances<LPV, CPL>(A, q, claim, nclaim, nkey);
+                    if (l2) distances<LPV, true>(A, qs, claim, nclaim, nkey);
+                    else distances<LPV, false>(A, qs, claim, nclaim, nkey);
                     __builtin_amdgcn_wave_barrier();
                     const uint64_t mk = lane < nclaim ? nkey[lane] : KEY_EMPTY;
                     __builtin_amdgcn_wave_barrier();
@@ -477,17 +548,11 @@ __device__ __forceinline__ void search_body(const KArgs &A)
                         uint32_t wm;
                         rl_get(ls, L - 1, worst, wm);
                     }
-                    const bool surv = lane < nclaim && mk < worst;
-                    uint64_t sbits = __ballot(surv);
+                    const uint64_t sbits = __ballot(lane < nclaim && mk < worst);
                     int U = L;
                     if (sbits) {
-                        U = rl_count_less(ls, wave_min64(surv ? mk : KEY_EMPTY));
-                        while (sbits) {
-                            const int j = __builtin_ctzll(sbits);
-                            sbits &= sbits - 1;
-                            rl_insert(ls, L, rdlane64(mk, j), META_SIDX | META_MINE);
-                            len = min(L, len + 1);
-                        }
+                        U = rl_insert_batch(ls, L, len, mk, sbits, nkey);
+                        len = min(L, len + __popcll(sbits));
                     }
                     cur = rl_first_expandable(ls);
                     epoch++;
@@ -549,7 +614,7 @@ __device__ __forceinline__ void search_body(const KArgs &A)
 
     // ------------------------------------------------------------ two or more workers
     int sb = 0;
-    if (MULTI && !C->done) {
+    if (!C->done) {
         int substeps = C->substeps, gsteps = C->gsteps, merges = C->merges;
         uint32_t epoch = (uint32_t)C->epoch;
         pv = -1;
@@ -610,18 +675,17 @@ __device__ __forceinline__ void search_body(const KArgs &A)
                         atomicAdd(&C->nexp, 1);
                     }
                     const int32_t v = key_id(vkey);
-                    if (v == pv) u = pu;
-                    else u = lane < R ? A.adj[(int64_t)v * R + lane] : -1;
+                    u = pu;
+                    if (v != pv) u = adj_lane[(int64_t)v * R];
                     const int nxt = rl_first_expandable(ls);
-                    pv = -1;
-                    if (nxt < len) {
-                        uint64_t nk;
+                    {
+                        uint64_t nk = vkey;
                         uint32_t nm;
-                        rl_get(ls, nxt, nk, nm);
+                        if (nxt < len) rl_get(ls, nxt, nk, nm);
                         pv = key_id(nk);
-                        pu = lane < R ? A.adj[(int64_t)pv * R + lane] : -1;
+                        pu = adj_lane[(int64_t)pv * R];
                     }
-                    if (u >= A.n) u = -1;
+                    if (lane >= R || u < 0 || u >= n) u = -1;
                     if (u >= 0) slot = mode ? visit_claim(gh, glog2, (uint32_t)u, tag, epoch, &fresh)
                                             : visit_claim(lh, llog2, (uint32_t)u, tag, epoch, &fresh);
                 }
@@ -642,7 +706,8 @@ __device__ __forceinline__ void search_body(const KArgs &A)
                     const int nclaim = __popcll(cm);
                     if (claimed) claim[__popcll(cm & lanemask_lt())] = u;
                     __builtin_amdgcn_wave_barrier();
-                    wave_distances<LPV, CPL>(A, q, claim, nclaim, nkey);
+                    if (l2) distances<LPV, true>(A, qs, claim, nclaim, nkey);
+                    else distances<LPV, false>(A, qs, claim, nclaim, nkey);
                     __builtin_amdgcn_wave_barrier();
                     const uint64_t mk = lane < nclaim ? nkey[lane] : KEY_EMPTY;
                     __builtin_amdgcn_wave_barrier();
@@ -651,16 +716,10 @@ __device__ __forceinline__ void search_body(const KArgs &A)
                         uint32_t wm;
                         rl_get(ls, L - 1, worst, wm);
                     }
-                    const bool surv = lane < nclaim && mk < worst;
-                    uint64_t sbits = __ballot(surv);
+                    const uint64_t sbits = __ballot(lane < nclaim && mk < worst);
                     if (sbits) {
-                        U = rl_count_less(ls, wave_min64(surv ? mk : KEY_EMPTY));
-                        while (sbits) {
-                            const int j = __builtin_ctzll(sbits);
-                            sbits &= sbits - 1;
-                            rl_insert(ls, L, rdlane64(mk, j), META_SIDX | META_MINE);
-                            len = min(L, len + 1);
-                        }
+                        U = rl_insert_batch(ls, L, len, mk, sbits, nkey);
+                        len = min(L, len + __popcll(sbits));
                     }
                     cur = rl_first_expandable(ls);
                 }

@@ -5,16 +5,16 @@
 namespace sa {
 namespace search_detail {
 
-template <int LPV, int CPL, int NI>
+template <int LPV, int NI>
 __global__ void __launch_bounds__(1024) search_multi(KArgs A)
 {
-    search_body<LPV, CPL, NI, true>(A);
+    search_body<LPV, NI>(A);
 }
 
-template <int LPV, int CPL, int NI>
+template <int LPV, int NI>
 hipError_t launch1(const KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s)
 {
-    auto k = search_multi<LPV, CPL, NI>;
+    auto k = search_multi<LPV, NI>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
@@ -22,16 +22,16 @@ hipError_t launch1(const KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t 
     return hipGetLastError();
 }
 
-template <int LPV, int CPL>
+template <int LPV>
 hipError_t launch1_ni(const KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s)
 {
     const int ni = (A.L + 63) / 64;
-    if (ni <= 1) return launch1<LPV, CPL, 1>(A, nq, M, lds, s);
-    if (ni <= 2) return launch1<LPV, CPL, 2>(A, nq, M, lds, s);
-    if (ni <= 4) return launch1<LPV, CPL, 4>(A, nq, M, lds, s);
-    if (ni <= 6) return launch1<LPV, CPL, 6>(A, nq, M, lds, s);
-    if (ni <= 8) return launch1<LPV, CPL, 8>(A, nq, M, lds, s);
-    return launch1<LPV, CPL, 16>(A, nq, M, lds, s);
+    if (ni <= 1) return launch1<LPV, 1>(A, nq, M, lds, s);
+    if (ni <= 2) return launch1<LPV, 2>(A, nq, M, lds, s);
+    if (ni <= 4) return launch1<LPV, 4>(A, nq, M, lds, s);
+    if (ni <= 6) return launch1<LPV, 6>(A, nq, M, lds, s);
+    if (ni <= 8) return launch1<LPV, 8>(A, nq, M, lds, s);
+    return launch1<LPV, 16>(A, nq, M, lds, s);
 }
 
 }  // namespace search_detail
@@ -39,14 +39,16 @@ hipError_t launch1_ni(const KArgs &A, int64_t nq, int M, uint32_t lds, hipStream
 int launch_search_multi(const search_detail::KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s)
 {
     using namespace search_detail;
-    const int nch = A.d / 4;
     hipError_t e;
-    if (nch <= 8) e = launch1_ni<8, 1>(A, nq, M, lds, s);
-    else if (nch <= 16) e = launch1_ni<16, 1>(A, nq, M, lds, s);
-    else if (nch <= 32) e = launch1_ni<32, 1>(A, nq, M, lds, s);
-    else if (nch <= 64) e = launch1_ni<64, 1>(A, nq, M, lds, s);
-    else if (nch <= 128) e = launch1_ni<64, 2>(A, nq, M, lds, s);
-    else e = launch1_ni<64, 4>(A, nq, M, lds, s);
+    switch (lanes_per_vector(A.d)) {
+    case 1: e = launch1_ni<1>(A, nq, M, lds, s); break;
+    case 2: e = launch1_ni<2>(A, nq, M, lds, s); break;
+    case 4: e = launch1_ni<4>(A, nq, M, lds, s); break;
+    case 8: e = launch1_ni<8>(A, nq, M, lds, s); break;
+    case 16: e = launch1_ni<16>(A, nq, M, lds, s); break;
+    case 32: e = launch1_ni<32>(A, nq, M, lds, s); break;
+    default: e = launch1_ni<64>(A, nq, M, lds, s); break;
+    }
     if (e != hipSuccess) return hip_fail(e, "search kernel launch");
     return SA_OK;
 }

@@ -27,48 +27,12 @@ namespace single_detail {
 
 using search_detail::KArgs;
 using search_detail::NO_SLOT;
+using search_detail::bpermute64;
+using search_detail::distances;
 using search_detail::hash_slot;
 using search_detail::lanemask_lt;
+using search_detail::low_bits;
 using search_detail::rdlane64;
-
-constexpr int DPP_ROW_SHR = 0x110;     // + n: row_shr:n
-constexpr int DPP_ROW_BCAST15 = 0x142;
-constexpr int DPP_ROW_BCAST31 = 0x143;
-
-// lanes whose DPP source is invalid (outside the row or the enabled rows) keep `old`
-template <int CTRL, int ROWMASK = 0xF>
-__device__ __forceinline__ uint32_t dpp32(uint32_t v, uint32_t old)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWMASK, 0xF, false);
-}
-
-template <int CTRL, int ROWMASK = 0xF>
-__device__ __forceinline__ double dpp_f64(double v)
-{
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = dpp32<CTRL, ROWMASK>((uint32_t)b, 0u);
-    const uint32_t hi = dpp32<CTRL, ROWMASK>((uint32_t)(b >> 32), 0u);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-// sum of each group of LPV lanes, left in the group's last lane
-template <int LPV>
-__device__ __forceinline__ double group_sum(double v)
-{
-    if constexpr (LPV >= 2) v += dpp_f64<DPP_ROW_SHR + 1>(v);
-    if constexpr (LPV >= 4) v += dpp_f64<DPP_ROW_SHR + 2>(v);
-    if constexpr (LPV >= 8) v += dpp_f64<DPP_ROW_SHR + 4>(v);
-    if constexpr (LPV >= 16) v += dpp_f64<DPP_ROW_SHR + 8>(v);
-    if constexpr (LPV >= 32) v += dpp_f64<DPP_ROW_BCAST15, 0xA>(v);
-    if constexpr (LPV >= 64) v += dpp_f64<DPP_ROW_BCAST31, 0xC>(v);
-    return v;
-}
-
-// bits [0, n) set, n in [0, 64]
-__device__ __forceinline__ uint64_t low_bits(int n)
-{
-    return n <= 0 ? 0ull : (n >= 64 ? ~0ull : (~0ull >> (64 - n)));
-}
 
 template <int NI>
 struct Queue {
@@ -117,13 +81,6 @@ __device__ __forceinline__ int count_less(const Queue<NI> &Q, uint64_t key)
 #pragma unroll
     for (int i = 0; i < NI; ++i) c += __popcll(__ballot(Q.k[i] < key));
     return c;
-}
-
-__device__ __forceinline__ uint64_t bpermute64(int addr, uint64_t v)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
 }
 
 // Inserts the unchecked keys mk of the lanes in sbits (distinct, none in the queue),
@@ -190,56 +147,6 @@ __device__ __forceinline__ int insert_batch(Queue<NI> &Q, int L, uint64_t mk, ui
     return fmin;
 }
 
-// Keys of the vectors ids[0..n) to out[0..n); qs is the query, zero padded to 16 LPV
-// floats.  Every load is issued unconditionally (from a clamped address, its value
-// dropped afterwards): loads under a lane condition each get their own wait, which would
-// turn one memory round trip into four.
-template <int LPV, int PB, bool L2>
-__device__ __forceinline__ void distances(const KArgs &A, const float *qs, const int32_t *ids, int n, uint64_t *out)
-{
-    constexpr int VPW = 64 / LPV;
-    const int lane = __lane_id(), grp = lane / LPV, g = lane % LPV;
-    const int nch = A.d >> 2;
-    for (int p0 = 0; p0 < n; p0 += VPW * PB) {
-        float4 x[PB][4];
-        int32_t id[PB];
-#pragma unroll
-        for (int pp = 0; pp < PB; ++pp) {
-            const int idx = p0 + pp * VPW + grp;
-            const int32_t raw = ids[idx & 63];
-            id[pp] = idx < n ? raw : -1;
-            const float *row = A.vec + (int64_t)(id[pp] < 0 ? 0 : id[pp]) * A.ld;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int c = g + LPV * i;
-                x[pp][i] = *reinterpret_cast<const float4 *>(row + 4 * (c < nch ? c : 0));
-            }
-        }
-#pragma unroll
-        for (int pp = 0; pp < PB; ++pp) {
-            double acc = 0.0;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const bool in = g + LPV * i < nch;
-                const float4 a = reinterpret_cast<const float4 *>(qs)[g + LPV * i];
-                const float bx = in ? x[pp][i].x : 0.f, by = in ? x[pp][i].y : 0.f;
-                const float bz = in ? x[pp][i].z : 0.f, bw = in ? x[pp][i].w : 0.f;
-                if constexpr (L2) {
-                    const double t0 = (double)a.x - (double)bx, t1 = (double)a.y - (double)by;
-                    const double t2 = (double)a.z - (double)bz, t3 = (double)a.w - (double)bw;
-                    acc += t0 * t0; acc += t1 * t1; acc += t2 * t2; acc += t3 * t3;
-                } else {
-                    acc += (double)a.x * (double)bx; acc += (double)a.y * (double)by;
-                    acc += (double)a.z * (double)bz; acc += (double)a.w * (double)bw;
-                }
-            }
-            acc = group_sum<LPV>(acc);
-            const int idx = p0 + pp * VPW + grp;
-            if (g == LPV - 1 && idx < n) out[idx] = make_key(L2 ? (float)acc : (float)(-acc), id[pp]);
-        }
-    }
-}
-
 // find or insert u; *fresh tells whether this call inserted it.  NO_SLOT: table full.
 __device__ __forceinline__ uint32_t claim(uint32_t *T, int log2cap, uint32_t u, bool *fresh)
 {
@@ -258,7 +165,7 @@ __device__ __forceinline__ uint32_t claim(uint32_t *T, int log2cap, uint32_t u, 
     return NO_SLOT;
 }
 
-template <int LPV, int NI, int PB, bool L2>
+template <int LPV, int NI, bool L2>
 __global__ void __launch_bounds__(64) search_single(KArgs A)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -295,7 +202,7 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
         Q.chk[i] = 0;
     }
     // dist(P, Q); P goes into the queue and the visited set
-    distances<LPV, PB, L2>(A, qs, sid, 1, nkey);
+    distances<LPV, L2>(A, qs, sid, 1, nkey);
     __builtin_amdgcn_wave_barrier();
     {
         const uint64_t k0 = nkey[0];
@@ -346,7 +253,7 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
             }
             nslot += nnew;
             __builtin_amdgcn_wave_barrier();
-            distances<LPV, PB, L2>(A, qs, sid, nnew, nkey);
+            distances<LPV, L2>(A, qs, sid, nnew, nkey);
             __builtin_amdgcn_wave_barrier();
             const uint64_t mk = lane < nnew ? nkey[lane] : KEY_EMPTY;
             __builtin_amdgcn_wave_barrier();
@@ -400,8 +307,7 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
 template <int LPV, int NI>
 hipError_t launch1(const KArgs &A, int64_t nq, hipStream_t s)
 {
-    constexpr int PB = 1;
-    auto k = A.metric == SA_L2 ? search_single<LPV, NI, PB, true> : search_single<LPV, NI, PB, false>;
+    auto k = A.metric == SA_L2 ? search_single<LPV, NI, true> : search_single<LPV, NI, false>;
     const uint32_t lds = 64 * 8 + 64 * 4 + 64 * LPV;
     hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64), lds, s, A);
     return hipGetLastError();
@@ -421,20 +327,11 @@ hipError_t launch1_ni(const KArgs &A, int64_t nq, hipStream_t s)
 
 }  // namespace single_detail
 
-// lanes per vector: the smallest power of two that leaves at most four float4 chunks per lane
-static int single_lanes_per_vector(int d)
-{
-    const int nch = d / 4;
-    int lpv = 1;
-    while (lpv < 64 && 4 * lpv < nch) lpv *= 2;
-    return lpv;
-}
-
 int launch_search_single(const search_detail::KArgs &A, int64_t nq, hipStream_t s)
 {
     using namespace single_detail;
     hipError_t e;
-    switch (single_lanes_per_vector(A.d)) {
+    switch (search_detail::lanes_per_vector(A.d)) {
     case 1: e = launch1_ni<1>(A, nq, s); break;
     case 2: e = launch1_ni<2>(A, nq, s); break;
     case 4: e = launch1_ni<4>(A, nq, s); break;
