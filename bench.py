@@ -204,22 +204,36 @@ def main():
         log(f"copy calibration: 3 x {args.copy_calibration_mib} MiB read + written")
 
     # ---------------------------------------------------------------- batch-1 latency
-    Mlat = max(s["M"] for s in sweep if s["recall"] >= TARGET) if reached else M
-    Llat = min([s["L"] for s in sweep if s["M"] == Mlat and s["recall"] >= TARGET] or [L])
+    # one query per launch, host wall time: every M's operating point (the smallest swept L
+    # at the recall target) on a short sample, then the best-p50 point on the full sample
     nl = min(args.latency_queries, args.nq)
-    lat = []
-    one = [(torch.empty((1, k), dtype=torch.int32, device=dev), torch.empty((1, k), dtype=torch.float32, device=dev),
-            None)]
-    for i in range(min(50, nl)):
-        run(Mlat, Llat, q=queries[i:i + 1], out=one[0])
-    torch.cuda.synchronize()
-    for i in range(nl):
-        q1 = queries[i:i + 1]
-        s0 = time.perf_counter()
-        run(Mlat, Llat, q=q1, out=one[0])
+    one = (torch.empty((1, k), dtype=torch.int32, device=dev), torch.empty((1, k), dtype=torch.float32, device=dev),
+           None)
+
+    def batch1(Mx, Lx, count):
+        for i in range(min(20, count)):
+            run(Mx, Lx, q=queries[i:i + 1], out=one)
         torch.cuda.synchronize()
-        lat.append((time.perf_counter() - s0) * 1e3)
-    lat = np.array(lat) if lat else np.array([float("nan")])
+        lat = []
+        for i in range(count):
+            q1 = queries[i:i + 1]
+            s0 = time.perf_counter()
+            run(Mx, Lx, q=q1, out=one)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - s0) * 1e3)
+        return np.array(lat) if lat else np.array([float("nan")])
+
+    ops = {s["M"]: s["L"] for s in sweep if s["recall"] >= TARGET} if reached else {M: L}
+    lat_by_M = {}
+    if nl > 0:
+        for Mx, Lx in sorted(ops.items()):
+            a = batch1(Mx, Lx, min(300, nl))
+            lat_by_M[Mx] = {"L": Lx, "p50_ms": round(float(np.percentile(a, 50)), 4),
+                            "p99_ms": round(float(np.percentile(a, 99)), 4), "queries": len(a)}
+            log(f"batch-1 latency sample M={Mx} L={Lx}: p50 {lat_by_M[Mx]['p50_ms']:.3f} ms")
+    Mlat = min(lat_by_M, key=lambda m: lat_by_M[m]["p50_ms"]) if lat_by_M else M
+    Llat = ops.get(Mlat, L)
+    lat = batch1(Mlat, Llat, nl)
     log(f"batch-1 latency M={Mlat} L={Llat}: p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
 
     # ---------------------------------------------------------------- roofline
@@ -279,6 +293,7 @@ def main():
             "p50_ms_batch1": round(float(np.percentile(lat, 50)), 4),
             "p99_ms_batch1": round(float(np.percentile(lat, 99)), 4),
             "batch1_point": {"M": Mlat, "L": Llat, "queries": nl},
+            "batch1_by_M": {str(m): v for m, v in sorted(lat_by_M.items())},
             "p50_ms_in_batch": round(float(np.percentile(svc_ms, 50)), 4),
             "p99_ms_in_batch": round(float(np.percentile(svc_ms, 99)), 4),
             "flagged_queries": int(((stats[:, 5] & 3) != 0).sum()),

@@ -3,6 +3,8 @@
 // (search_multi.hip, whose body is in search_body.h).
 #include "search_body.h"
 
+#include <algorithm>
+
 namespace sa {
 namespace {
 
@@ -10,12 +12,12 @@ using search_detail::Ctrl;
 using search_detail::KArgs;
 
 struct Layout {
-    uint32_t o_skey, o_srank, o_schk, o_lskey, o_lsmeta, o_newkey, o_claim, o_ctrl, o_hash, o_q, total;
+    uint32_t o_skey, o_srank, o_schk, o_pub, o_newkey, o_claim, o_ctrl, o_hash, o_q, total;
 };
 
 uint32_t align_up(uint32_t x, uint32_t a) { return (x + a - 1) / a * a; }
 
-// S, the rank array and the LDS copies of the local queues exist only with M >= 2; the
+// S, the rank array and the published new keys of a merge exist only with M >= 2; the
 // query takes 16 floats per lane of a vector group
 Layout make_layout(int L, int M, int llog2, int lpv)
 {
@@ -25,8 +27,7 @@ Layout make_layout(int L, int M, int llog2, int lpv)
     Y.o_skey = o; o += 2u * 8u * LL;
     Y.o_srank = o; o += 4u * LL;
     Y.o_schk = o; o = align_up(o + 2u * LL, 16);
-    Y.o_lskey = o; o += 8u * M * LL;
-    Y.o_lsmeta = o; o += 4u * M * LL;
+    Y.o_pub = o; o += M >= 2 ? 8u * search_detail::PUBCAP : 0u;
     o = align_up(o, 16);
     Y.o_newkey = o; o += 8u * 64u * M;
     Y.o_claim = o; o += 4u * 64u * M;
@@ -54,7 +55,18 @@ void resolve_params(const sa_search_params &in, int L, int M, int R, int &llog2,
     max_sub = in.max_substeps > 0 ? in.max_substeps : (1 << 22);
     if (in.lds_hash_slots > 0) llog2 = ilog2_exact(in.lds_hash_slots);
     else if (in.lds_hash_slots < 0) llog2 = 0;
-    else llog2 = M <= 2 ? 0 : 12;   // one or two workers: favour occupancy over LDS latency
+    else if (M <= 2) llog2 = 0;     // one or two workers: favour occupancy over LDS latency
+    else if (M < 8) llog2 = 12;
+    else {
+        // eight or more workers are for latency: a table of about 16 L slots keeps the
+        // visited set (some 8 L vertices) in LDS, if the layout leaves room for it
+        llog2 = 12;
+        for (int lg = ilog2_exact(std::min<int64_t>(16ll * L, 1 << 14)); lg > 12; --lg)
+            if (make_layout(L, M, lg, 64).total <= 160u * 1024u) {
+                llog2 = lg;
+                break;
+            }
+    }
     if (in.ws_hash_slots > 0) glog2 = ilog2_exact(in.ws_hash_slots);
     else {
         // the visited set holds at most 1 + E * R vertices after E expansions, and E stays
@@ -107,8 +119,8 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     A.d = a.d; A.metric = a.metric; A.R = a.R; A.entry = a.entry; A.k = a.k; A.L = a.L; A.M = a.M;
     A.sync = a.p.sync; A.static_I = a.p.static_I; A.staged = a.p.staged ? 1 : 0; A.max_substeps = max_sub;
     A.rho = a.p.rho; A.glog2 = glog2; A.llog2 = llog2;
-    A.o_skey = Y.o_skey; A.o_srank = Y.o_srank; A.o_schk = Y.o_schk; A.o_lskey = Y.o_lskey;
-    A.o_lsmeta = Y.o_lsmeta; A.o_newkey = Y.o_newkey; A.o_claim = Y.o_claim; A.o_ctrl = Y.o_ctrl;
+    A.o_skey = Y.o_skey; A.o_srank = Y.o_srank; A.o_schk = Y.o_schk; A.o_pub = Y.o_pub;
+    A.o_newkey = Y.o_newkey; A.o_claim = Y.o_claim; A.o_ctrl = Y.o_ctrl;
     A.o_hash = Y.o_hash; A.o_q = Y.o_q;
     if (a.nq == 0) return SA_OK;
     if (a.d > 1024) return set_error(SA_EUNSUPPORTED, "d=%d exceeds 1024", a.d);

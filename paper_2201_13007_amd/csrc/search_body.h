@@ -41,10 +41,10 @@ constexpr uint32_t META_SIDX = 0xFFFFu;
 constexpr uint32_t META_MINE = 1u << 16;
 constexpr uint32_t META_CHK = 1u << 17;
 constexpr int MAXW = 16;
+constexpr int PUBCAP = 512;   // new keys published per round of a merge
 constexpr uint32_t NO_SLOT = 0xFFFFFFFFu;
 
 struct Ctrl {
-    int32_t lslen[MAXW];
     int32_t U[MAXW];
     int32_t work[MAXW];
     int32_t nnew[MAXW];
@@ -73,7 +73,7 @@ struct KArgs {
     int32_t d, metric, R, entry, k, L, M, sync, static_I, staged, max_substeps;
     double rho;
     int32_t glog2, llog2;        // llog2 == 0: no LDS table
-    uint32_t o_skey, o_srank, o_schk, o_lskey, o_lsmeta, o_newkey, o_claim, o_ctrl, o_hash, o_q;
+    uint32_t o_skey, o_srank, o_schk, o_pub, o_newkey, o_claim, o_ctrl, o_hash, o_q;
 };
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
@@ -408,9 +408,7 @@ __device__ __forceinline__ void search_body(const KArgs &A)
     uint64_t *const skey_base = reinterpret_cast<uint64_t *>(smem + A.o_skey);
     int32_t *const srank = reinterpret_cast<int32_t *>(smem + A.o_srank);
     uint8_t *const schk_base = smem + A.o_schk;
-    uint64_t *const lskey_all = reinterpret_cast<uint64_t *>(smem + A.o_lskey);
-    uint64_t *const lskey = lskey_all + (size_t)w * L;
-    uint32_t *const lsmeta = reinterpret_cast<uint32_t *>(smem + A.o_lsmeta) + (size_t)w * L;
+    uint64_t *const pub = reinterpret_cast<uint64_t *>(smem + A.o_pub);   // [PUBCAP] published new keys
     uint64_t *const nkey = reinterpret_cast<uint64_t *>(smem + A.o_newkey) + w * 64;
     int32_t *const claim = reinterpret_cast<int32_t *>(smem + A.o_claim) + w * 64;
     Ctrl *const C = reinterpret_cast<Ctrl *>(smem + A.o_ctrl);
@@ -726,16 +724,14 @@ __device__ __forceinline__ void search_body(const KArgs &A)
                 if (lane == 0 && w < m) {
                     C->U[w] = U;
                     C->work[w] = cur < len;
-                    C->lslen[w] = len;
                 }
                 epoch++;
                 __syncthreads();
-                bool any = false;
-                int64_t sumU = 0;
-                for (int t = 0; t < m; ++t) {
-                    any = any || C->work[t] != 0;
-                    sumU += C->U[t];
-                }
+                // lane t reads worker t's flag and update position
+                const bool any = __ballot(lane < m && C->work[lane] != 0) != 0;
+                int sumU = lane < m ? C->U[lane] : 0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) sumU += __shfl_xor(sumU, off, 64);
                 bool merge_now;
                 if (A.sync == SA_SYNC_BSP) merge_now = true;
                 else if (A.sync == SA_SYNC_STATIC) merge_now = A.static_I > 0 && sub_in_step >= A.static_I;
@@ -768,51 +764,84 @@ __device__ __forceinline__ void search_body(const KArgs &A)
             // entry's rank is its index plus, per worker, the new entries ahead of it in
             // that worker's queue (L if the worker truncated it away); a new entry's rank
             // is its position in its own queue plus the new entries of the other workers
-            // below it.
-            if (w < m) {
-#pragma unroll
-                for (int i = 0; i < NI; ++i) {
-                    const int p = i * 64 + lane;
-                    if (p < len) {
-                        lskey[p] = ls.k[i];
-                        lsmeta[p] = ls.m[i];
-                    }
-                }
-            }
-            __syncthreads();
+            // below it.  A vertex is claimed by one worker only, so all new entries are
+            // distinct keys: every worker publishes its own to LDS (PUBCAP at a time) and
+            // each new entry counts the published keys below it, its own included.
             uint64_t *Sn = skey_base + (sb ^ 1) * L;
             uint8_t *Snc = schk_base + (sb ^ 1) * L;
             if (w < m) {
-                int nbefore = 0;
+                int own = 0;
 #pragma unroll
                 for (int i = 0; i < NI; ++i) {
                     const int p = i * 64 + lane;
                     const bool valid = p < len;
-                    const uint32_t meta = valid ? ls.m[i] : 0u;
-                    const uint32_t sidx = meta & META_SIDX;
-                    const bool isS = valid && sidx != META_SIDX;
-                    const bool isN = valid && sidx == META_SIDX;
-                    if (isS) atomicAdd(&srank[sidx], p - (int)sidx - L);
-                    const uint64_t nm = __ballot(isN);
-                    if (isN) {
-                        const int nidx = nbefore + __popcll(nm & lanemask_lt());
-                        const uint64_t key = ls.k[i];
-                        const int cS = p - nidx;
-                        int rank = p;
-                        for (int t = 0; t < m && rank < L; ++t) {
-                            if (t == w) continue;
-                            rank += lower_bound(lskey_all + (size_t)t * L, C->lslen[t], key) - cS;
-                        }
-                        if (rank < L) {
-                            Sn[rank] = key;
-                            Snc[rank] = (meta & META_CHK) ? 1 : 0;
-                        }
-                    }
-                    nbefore += __popcll(nm);
+                    const uint32_t sidx = valid ? ls.m[i] & META_SIDX : 0u;
+                    if (valid && sidx != META_SIDX) atomicAdd(&srank[sidx], p - (int)sidx - L);
+                    own += __popcll(__ballot(valid && sidx == META_SIDX));
                 }
-                if (lane == 0) C->nnew[w] = nbefore;
+                if (lane == 0) C->nnew[w] = own;
             }
             __syncthreads();
+            int first = 0, total_new = 0;   // this worker's place in the published order
+#pragma unroll
+            for (int t = 0; t < MAXW; ++t) {
+                const int nn = t < m ? C->nnew[t] : 0;
+                first += t < w ? nn : 0;
+                total_new += nn;
+            }
+            int rk[NI];   // own position - own new entries below + published keys below
+            {
+                int nb = 0;
+#pragma unroll
+                for (int i = 0; i < NI; ++i) {
+                    const int p = i * 64 + lane;
+                    const bool isN = w < m && p < len && (ls.m[i] & META_SIDX) == META_SIDX;
+                    const uint64_t nm = __ballot(isN);
+                    rk[i] = p - (nb + __popcll(nm & lanemask_lt()));
+                    nb += __popcll(nm);
+                }
+            }
+            for (int c0 = 0; c0 < total_new; c0 += PUBCAP) {
+                const int cn = min(PUBCAP, total_new - c0);
+                if (w < m) {
+                    int nb = first;
+#pragma unroll
+                    for (int i = 0; i < NI; ++i) {
+                        const int p = i * 64 + lane;
+                        const bool isN = p < len && (ls.m[i] & META_SIDX) == META_SIDX;
+                        const uint64_t nm = __ballot(isN);
+                        const int g = nb + __popcll(nm & lanemask_lt()) - c0;
+                        if (isN && g >= 0 && g < cn) pub[g] = ls.k[i];
+                        nb += __popcll(nm);
+                    }
+                }
+                __syncthreads();
+                if (w < m) {
+#pragma unroll
+                    for (int i = 0; i < NI; ++i) {
+                        const int p = i * 64 + lane;
+                        const bool isN = p < len && (ls.m[i] & META_SIDX) == META_SIDX;
+                        if (__ballot(isN)) {
+                            const uint64_t key = ls.k[i];
+                            int below = 0;
+                            for (int j = 0; j < cn; ++j) below += pub[j] < key ? 1 : 0;
+                            rk[i] += below;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            if (w < m) {
+#pragma unroll
+                for (int i = 0; i < NI; ++i) {
+                    const int p = i * 64 + lane;
+                    const bool isN = p < len && (ls.m[i] & META_SIDX) == META_SIDX;
+                    if (isN && rk[i] < L) {
+                        Sn[rk[i]] = ls.k[i];
+                        Snc[rk[i]] = (ls.m[i] & META_CHK) ? 1 : 0;
+                    }
+                }
+            }
             for (int j = tid; j < slen; j += nthr) {
                 const int r = srank[j];
                 if (r < L) {
@@ -820,10 +849,8 @@ __device__ __forceinline__ void search_body(const KArgs &A)
                     Snc[r] = Sc[j];
                 }
             }
-            int total = slen;
-            for (int t = 0; t < m; ++t) total += C->nnew[t];
             __syncthreads();
-            if (tid == 0) C->slen = min(L, total);
+            if (tid == 0) C->slen = min(L, slen + total_new);
             sb ^= 1;
             merges++;
             if (A.staged && m < M) m = min(2 * m, M);
