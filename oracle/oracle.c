@@ -23,6 +23,9 @@
  *                     worker order, against one exact shared visited set
  *   graph helpers     medoid, row pruning, connectivity repair (graph construction is
  *                     outside the paper, which takes an NSG graph as given, Sec. 2.2)
+ *   reduced precision vector storage in bf16 or fp8 e4m3 with a per-vector scale, and
+ *                     the exact re-rank of a final candidate list (outside the paper,
+ *                     which stores float32): or_quantize, or_dequantize, or_rerank
  *
  * Readings where the paper is silent (each listed in the design notes):
  *   - the starting point is marked visited when it is added (Algorithm 1 adds it
@@ -751,4 +754,116 @@ int64_t or_reachable(const int32_t *adj, int R, int64_t n, int32_t src, uint8_t 
     free(queue);
     if (!mark_out) free(mark);
     return c;
+}
+
+/* ---------------------------------------------------------------- reduced precision
+ *
+ * Storage formats, from their definitions (not part of the paper):
+ *   OR_BF16  the upper half of the float32 pattern, rounded to nearest even; no scale
+ *            (bf16 keeps float32's exponent range, so a scale would change nothing).
+ *   OR_FP8   e4m3 with finite values only: sign, 4 exponent bits (bias 7), 3 mantissa
+ *            bits; exponent field 0 holds subnormals m * 2^-9, the pattern S.1111.111 is
+ *            not a number, so the largest value is 1.75 * 2^8 = 448.  Each vector gets the
+ *            scale amax / 448 (1 for a zero vector); a coordinate is divided by it in
+ *            float, rounded to nearest even and saturated at 448.
+ * A stored coordinate stands for scale * value(code), computed in float (one rounding). */
+
+#define OR_F32 0
+#define OR_BF16 1
+#define OR_FP8 2
+
+static uint16_t bf16_encode(float x)
+{
+    uint32_t b;
+    memcpy(&b, &x, 4);
+    if ((b & 0x7F800000u) == 0x7F800000u && (b & 0x007FFFFFu)) return (uint16_t)((b >> 16) | 0x40u);
+    b += 0x7FFFu + ((b >> 16) & 1u);   /* nearest, ties to the even upper half */
+    return (uint16_t)(b >> 16);
+}
+
+static float bf16_decode(uint16_t c)
+{
+    uint32_t b = (uint32_t)c << 16;
+    float x;
+    memcpy(&x, &b, 4);
+    return x;
+}
+
+static uint8_t fp8_encode(float x)
+{
+    const uint8_t sign = signbit(x) ? 0x80 : 0x00;
+    double a = fabs((double)x);
+    if (!(a < 448.0)) return (uint8_t)(sign | 0x7E);   /* saturate (NaN included) */
+    int e2;
+    (void)frexp(a, &e2);   /* a = f * 2^e2, f in [0.5, 1) */
+    int E = e2 - 1;        /* a in [2^E, 2^(E+1)) */
+    if (a == 0.0 || E < -6) {
+        double m = nearbyint(a / ldexp(1.0, -9));   /* subnormal units, ties to even */
+        return (uint8_t)(sign | (uint8_t)m);         /* m == 8 is the smallest normal */
+    }
+    double m = nearbyint((a / ldexp(1.0, E) - 1.0) * 8.0);
+    if (m == 8.0) { m = 0.0; E += 1; }
+    if (E > 8 || (E == 8 && m > 6.0)) return (uint8_t)(sign | 0x7E);
+    return (uint8_t)(sign | (uint8_t)((E + 7) << 3) | (uint8_t)m);
+}
+
+static float fp8_decode(uint8_t c)
+{
+    const int e = (c >> 3) & 0xF, m = c & 7;
+    double v = e == 0 ? ldexp((double)m, -9) : ldexp(1.0 + m / 8.0, e - 7);
+    if (e == 15 && m == 7) v = NAN;
+    return (float)((c & 0x80) ? -v : v);
+}
+
+/* codes: n rows of d codes (2 bytes for bf16, 1 for fp8), dense; scale: n floats */
+void or_quantize(const float *x, int64_t n, int d, int64_t ld, int dtype, void *codes, float *scale)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const float *r = x + i * ld;
+        if (dtype == OR_BF16) {
+            uint16_t *c = (uint16_t *)codes + i * d;
+            for (int j = 0; j < d; ++j) c[j] = bf16_encode(r[j]);
+            scale[i] = 1.0f;
+        } else {
+            uint8_t *c = (uint8_t *)codes + i * d;
+            float amax = 0.0f;
+            for (int j = 0; j < d; ++j) amax = fmaxf(amax, fabsf(r[j]));
+            const float s = amax > 0.0f ? amax / 448.0f : 1.0f;
+            for (int j = 0; j < d; ++j) c[j] = fp8_encode(r[j] / s);
+            scale[i] = s;
+        }
+    }
+}
+
+/* the float32 values the codes stand for: out[i][j] = scale[i] * value(code) */
+void or_dequantize(const void *codes, const float *scale, int64_t n, int d, int dtype, float *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int j = 0; j < d; ++j) {
+            const float v = dtype == OR_BF16 ? bf16_decode(((const uint16_t *)codes)[i * d + j])
+                                             : fp8_decode(((const uint8_t *)codes)[i * d + j]);
+            out[i * d + j] = dtype == OR_BF16 ? v : scale[i] * v;
+        }
+}
+
+/* Exact re-rank: each query's candidate list cand[q][0..L) (-1 padded) gets its distances
+ * recomputed on base (float32) and the first k by key are written out, (-1, +inf) padded. */
+void or_rerank(const float *base, int d, int64_t ld, int metric, const float *queries, int64_t nq, int64_t ldq,
+               const int32_t *cand, int L, int k, int32_t *ids, float *dists)
+{
+    entry *e = (entry *)malloc(sizeof(entry) * (size_t)(L > 0 ? L : 1));
+    for (int64_t q = 0; q < nq; ++q) {
+        int64_t cnt = 0;
+        for (int j = 0; j < L; ++j) {
+            const int32_t id = cand[q * L + j];
+            if (id < 0) continue;
+            e[cnt].dist = or_distance(queries + q * ldq, base + (int64_t)id * ld, d, metric);
+            e[cnt].id = id;
+            e[cnt].state = 0;
+            cnt++;
+        }
+        qsort(e, (size_t)cnt, sizeof(entry), entry_cmp);
+        emit(e, cnt, k, ids + q * k, dists + q * k);
+    }
+    free(e);
 }

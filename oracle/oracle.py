@@ -74,6 +74,13 @@ def lib():
         L.or_reverse_edges.argtypes = [f32p, i64, C.c_int, i64, C.c_int, i32p, C.c_int]
         L.or_reverse_edges.restype = i64
         L.or_reachable.argtypes = [i32p, C.c_int, i64, i32, u8p]
+        vp = C.c_void_p
+        L.or_quantize.argtypes = [f32p, i64, C.c_int, i64, C.c_int, vp, f32p]
+        L.or_quantize.restype = None
+        L.or_dequantize.argtypes = [vp, f32p, i64, C.c_int, C.c_int, f32p]
+        L.or_dequantize.restype = None
+        L.or_rerank.argtypes = [f32p, C.c_int, i64, C.c_int, f32p, i64, i64, i32p, C.c_int, C.c_int, i32p, f32p]
+        L.or_rerank.restype = None
         L.or_reachable.restype = i64
         _lib = L
     return _lib
@@ -233,3 +240,38 @@ def recall(found_ids, true_ids, k=None) -> np.ndarray:
         f = set(int(x) for x in found_ids[i, :k] if x >= 0)
         out[i] = len(t & f) / float(k)
     return out
+
+
+DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
+
+
+def quantize(x, dtype):
+    """Codes (uint16 for bf16, uint8 for fp8 e4m3) and per-vector scales of the rows of x."""
+    x = _f32(x)
+    n, d = x.shape
+    codes = np.empty((n, d), np.uint16 if dtype == "bf16" else np.uint8)
+    scale = np.empty(n, np.float32)
+    lib().or_quantize(x, n, d, d, DTYPES[dtype], codes.ctypes.data, scale)
+    return codes, scale
+
+
+def dequantize(codes, scale, dtype):
+    """The float32 vectors the codes stand for (scale * value, one float rounding)."""
+    codes = np.ascontiguousarray(codes)
+    scale = np.ascontiguousarray(scale, dtype=np.float32)
+    n, d = codes.shape
+    out = np.empty((n, d), np.float32)
+    lib().or_dequantize(codes.ctypes.data, scale, n, d, DTYPES[dtype], out)
+    return out
+
+
+def rerank(base, queries, cand, k, metric="l2"):
+    """Exact re-rank of each query's candidate ids (-1 padded) on float32 base: first k by key."""
+    base, queries = _f32(base), _f32(queries)
+    cand = np.ascontiguousarray(cand, dtype=np.int32)
+    nq, L = cand.shape
+    ids = np.empty((nq, k), np.int32)
+    dists = np.empty((nq, k), np.float32)
+    lib().or_rerank(base, base.shape[1], base.shape[1], _metric(metric), queries, nq, queries.shape[1], cand, L, k,
+                    ids, dists)
+    return ids, dists

@@ -344,3 +344,103 @@ def test_repair_hubs_are_nearest_to_mean():
     assert adj[4].tolist() == [3, 6, -1]
     assert adj[2].tolist()[:2] == [1, 3]
     assert oracle.reachable(adj, 4)[0] == 8
+
+
+# ------------------------------------------------------------------ reduced precision storage
+# Pins from the format definitions: bf16 = upper half of the float32 pattern rounded to
+# nearest even; fp8 e4m3 (finite): bias 7, 3 mantissa bits, subnormals m * 2^-9, largest
+# 448; per-vector scale amax / 448 for fp8.
+
+def test_bf16_codes_hand_cases():
+    x = np.array([[1.0, 1.0 + 2**-8, 1.0 + 3 * 2**-8, -2.5, 2.0**-130, 65504.0]], np.float32)
+    codes, scale = oracle.quantize(x, "bf16")
+    # 1+2^-8 is a tie between 0x3F80 and 0x3F81: even wins; 1+3*2^-8 ties 0x3F81/0x3F82
+    # 2^-130 is the float32 subnormal 2^19 * 2^-149 (pattern 0x00080000); 65504 rounds up
+    assert [int(c) for c in codes[0]] == [0x3F80, 0x3F80, 0x3F82, 0xC020, 0x0008, 0x4780]
+    assert scale[0] == 1.0
+    back = oracle.dequantize(codes, scale, "bf16")
+    assert back[0, 0] == 1.0 and back[0, 3] == -2.5 and back[0, 5] == 65536.0
+
+
+def _e4m3_value(c):
+    """Value of an e4m3 code from the definition (independent of the oracle)."""
+    e, m = (c >> 3) & 15, c & 7
+    v = m * 2.0**-9 if e == 0 else (1 + m / 8) * 2.0 ** (e - 7)
+    return -v if c & 0x80 else v
+
+
+def test_fp8_codes_hand_cases():
+    # 448 in the row makes the scale exactly 1
+    x = np.array([[448.0, 1.0, 0.5, 1.0625, 1.1875, -1.0, 240.0, 2**-9, 2**-10, 3 * 2**-10, 0.0, -0.0]],
+                 np.float32)
+    codes, scale = oracle.quantize(x, "fp8")
+    assert scale[0] == 1.0
+    # 1.0625 ties 1.0 / 1.125 -> even mantissa 0; 1.1875 ties 1.125 / 1.25 -> mantissa 2;
+    # 2^-10 ties 0 / 2^-9 -> 0; 3 * 2^-10 ties 2^-9 / 2^-8 -> 2 * 2^-9
+    assert [int(c) for c in codes[0]] == [0x7E, 0x38, 0x30, 0x38, 0x3A, 0xB8, 0x77, 0x01, 0x00, 0x02, 0x00, 0x80]
+
+
+def test_fp8_every_finite_code_round_trips():
+    finite = [c for c in range(256) if (c & 0x7F) != 0x7F]
+    assert len(finite) == 254
+    vals = np.array([_e4m3_value(c) for c in finite], np.float32)
+    row = np.concatenate([[448.0], vals]).astype(np.float32)[None, :]
+    codes, scale = oracle.quantize(row, "fp8")
+    assert scale[0] == 1.0
+    got = [int(c) for c in codes[0, 1:]]
+    # -0 and +0 both decode to zero; every other code must come back unchanged
+    assert [g for g, c in zip(got, finite) if c != 0x80] == [c for c in finite if c != 0x80]
+    back = oracle.dequantize(codes, scale, "fp8")[0, 1:]
+    np.testing.assert_array_equal(back, vals)
+
+
+def test_fp8_scale_and_error_bound():
+    rng = np.random.default_rng(3)
+    x = (rng.standard_normal((200, 96)) * rng.uniform(0.01, 100, (200, 1))).astype(np.float32)
+    codes, scale = oracle.quantize(x, "fp8")
+    amax = np.abs(x).max(1)
+    np.testing.assert_array_equal(scale, (amax / np.float32(448.0)).astype(np.float32))
+    back = oracle.dequantize(codes, scale, "fp8").astype(np.float64)
+    t = np.abs(x.astype(np.float64)) / scale[:, None]
+    # half a unit in the last place of the e4m3 binade of |x| / s (2^-10 in the subnormal
+    # range), times the scale, plus the float roundings of the division and the product
+    ulp = np.where(t < 2**-6, 2.0**-9, 2.0 ** (np.floor(np.log2(np.maximum(t, 2**-6))) - 3))
+    bound = (ulp / 2 * (1 + 2**-20) + t * 2**-23) * scale[:, None] + np.abs(back) * 2**-24
+    assert (np.abs(back - x) <= bound).all()
+    # the largest magnitude of every row is represented exactly up to the product rounding
+    i = np.abs(x).argmax(1)
+    np.testing.assert_allclose(np.abs(back[np.arange(200), i]), amax, rtol=2**-23)
+
+
+def test_bf16_error_bound():
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((100, 64)).astype(np.float32)
+    codes, scale = oracle.quantize(x, "bf16")
+    back = oracle.dequantize(codes, scale, "bf16").astype(np.float64)
+    assert (np.abs(back - x) <= np.abs(x) * 2.0**-8).all()
+
+
+def test_rerank_is_brute_force_over_the_candidates():
+    w = synth.tiny()
+    base, q = w.base[:3000], w.queries[:20]
+    rng = np.random.default_rng(5)
+    cand = np.stack([rng.choice(3000, 50, replace=False) for _ in range(20)]).astype(np.int32)
+    cand[:, -5:] = -1
+    ids, dists = oracle.rerank(base, q, cand, 10)
+    for i in range(20):
+        c = cand[i][cand[i] >= 0]
+        dd = np.array([oracle.distance(q[i], base[j]) for j in c], np.float32)
+        order = np.lexsort((c, dd))[:10]
+        np.testing.assert_array_equal(ids[i], c[order])
+        np.testing.assert_array_equal(dists[i], dd[order])
+
+
+def test_rerank_on_the_search_base_keeps_the_search_result():
+    w = synth.tiny()
+    base, q = w.base[:4000], w.queries[:25]
+    adj, entry, _ = oracle.build_graph(base, 32, 24, "rng", do_repair=True)
+    full, _, _ = oracle.speedann(base, adj, entry, q, 64, 64, 4)     # k = L: the final list
+    top, tdist, _ = oracle.speedann(base, adj, entry, q, 10, 64, 4)
+    ids, dists = oracle.rerank(base, q, full, 10)
+    np.testing.assert_array_equal(ids, top)
+    np.testing.assert_array_equal(dists, tdist)
