@@ -42,7 +42,8 @@ def recall_at_k(ids, gt, k):
 
 # every source that goes into the search kernels: measured traffic is reported only while
 # these files are unchanged
-SEARCH_SOURCES = ("search.hip", "sa_internal.h", "search_body.h", "search_single.hip", "search_multi.hip")
+SEARCH_SOURCES = ("search.hip", "sa_internal.h", "search_body.h", "search_single.h", "search_single_f32.hip",
+                  "search_multi.h", "search_multi_f32.hip")
 
 
 def kernel_source_hash():

@@ -39,6 +39,16 @@ typedef enum {
 
 typedef enum { SA_L2 = 0, SA_IP = 1 } sa_metric;
 
+/* Vector storage of an index (not from the paper, which stores float32):
+ *   SA_F32      float32
+ *   SA_BF16     bfloat16: the upper half of the float32 pattern rounded to nearest even;
+ *               no scale (a value is its code)
+ *   SA_FP8E4M3  8-bit e4m3, finite variant (bias 7, 3 mantissa bits, subnormals m * 2^-9,
+ *               largest 448, no infinities) with a float32 scale per vector: a coordinate
+ *               stands for scale * value(code), computed in float32.
+ * Distances are computed on these values exactly as on float32 vectors. */
+typedef enum { SA_F32 = 0, SA_BF16 = 1, SA_FP8E4M3 = 2 } sa_dtype;
+
 /* Synchronisation schedule of the local searches (Algorithm 3, CheckMetrics):
  *   SA_SYNC_BSP       merge the local queues after every local step (the Top-M scheme
  *                     of Sec. 4.1, bulk synchronous)
@@ -64,6 +74,10 @@ typedef struct {
                                of it moves the set to the workspace. */
     int32_t ws_hash_slots;  /* visited-set slots per query in the workspace, power of two;
                                0 = chosen from L and M */
+    int32_t rerank;         /* 0 (default): none.  > 0: the first min(rerank, |S|) entries of the
+                               final list get exact distances from the index's float32 vectors
+                               and the first k of them by key are returned; -1: the whole final
+                               list.  Needs float32 vectors in the index (SA_EINVAL otherwise). */
 } sa_search_params;
 
 /* Per-query counters written by sa_search when stats_dev is not NULL. */
@@ -181,6 +195,23 @@ int sa_build_graph(const float *base_dev, int64_t n, int32_t d, int64_t ld, int3
 int sa_index_create(const float *vec_dev, int64_t n, int32_t d, int64_t ld, int32_t metric,
                     const int32_t *adj_dev, int32_t R, int32_t entry, sa_index **out);
 void sa_index_destroy(sa_index *index);
+
+/* Reduced-precision copy of n vectors (rows of d float32, stride ld, 16-byte aligned):
+ *   dtype      SA_BF16 or SA_FP8E4M3
+ *   codes_dev  n rows of ldc codes (2 bytes each for bf16, 1 for fp8), ldc >= d,
+ *              ldc % 4 == 0, 16-byte aligned; columns d..ldc-1 get code 0
+ *   scale_dev  n floats: amax / 448 per vector for fp8 (1 for a zero vector), 1 for bf16
+ * Codes round to nearest even; fp8 saturates at 448.  Enqueued on hip_stream. */
+int sa_quantize(const float *x_dev, int64_t n, int32_t d, int64_t ld, int32_t dtype, void *codes_dev, int64_t ldc,
+                float *scale_dev, void *hip_stream);
+
+/* sa_index_create for any storage: codes_dev holds n rows of ldc elements of dtype (for
+ * SA_F32 the float32 vectors, 16-byte aligned, ldc % 4 == 0), scale_dev the fp8 scales
+ * (ignored otherwise), vec32_dev (may be NULL) the float32 vectors with stride ld32, read
+ * only by the re-rank.  The index borrows every array. */
+int sa_index_create_q(const void *codes_dev, int32_t dtype, const float *scale_dev, int64_t ldc,
+                      const float *vec32_dev, int64_t ld32, int64_t n, int32_t d, int32_t metric,
+                      const int32_t *adj_dev, int32_t R, int32_t entry, sa_index **out);
 
 /* Bytes of workspace sa_search needs for nq queries (visited sets that outgrow LDS). */
 size_t sa_search_workspace_bytes(const sa_index *index, int64_t nq, int32_t k, int32_t L, int32_t M,

@@ -19,13 +19,14 @@ SA_L2, SA_IP = 0, 1
 SYNC = {"bsp": 0, "static": 1, "adaptive": 2}
 QFLAG_MAX_STEPS, QFLAG_CAPACITY, QFLAG_SPILLED = 1, 2, 4
 
-EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_medoid", "sa_prune", "sa_reverse_edges",
+EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_quantize", "sa_index_create_q", "sa_medoid", "sa_prune", "sa_reverse_edges",
            "sa_repair", "sa_build_graph", "sa_index_create", "sa_index_destroy", "sa_search_workspace_bytes", "sa_search"]
 
 
 class SearchParams(C.Structure):
     _fields_ = [("sync", C.c_int32), ("static_I", C.c_int32), ("rho", C.c_double), ("staged", C.c_int32),
-                ("max_substeps", C.c_int32), ("lds_hash_slots", C.c_int32), ("ws_hash_slots", C.c_int32)]
+                ("max_substeps", C.c_int32), ("lds_hash_slots", C.c_int32), ("ws_hash_slots", C.c_int32),
+                ("rerank", C.c_int32)]
 
 
 # sa_query_stats as a numpy/torch view: 6 int32 + 2 uint64 = 40 bytes
@@ -60,12 +61,14 @@ def lib():
         L.sa_build_graph.argtypes = [vp, i64, i32, i64, i32, i32, i32, i32, i32, i32, i32, i32, vp,
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp]
         L.sa_index_create.argtypes = [vp, i64, i32, i64, i32, vp, i32, i32, C.POINTER(vp)]
+        L.sa_index_create_q.argtypes = [vp, i32, vp, i64, vp, i64, i64, i32, i32, vp, i32, i32, C.POINTER(vp)]
+        L.sa_quantize.argtypes = [vp, i64, i32, i64, i32, vp, i64, vp, vp]
         L.sa_index_destroy.argtypes = [vp]
         L.sa_index_destroy.restype = None
         L.sa_search_workspace_bytes.argtypes = [vp, i64, i32, i32, i32, C.POINTER(SearchParams)]
         L.sa_search_workspace_bytes.restype = sz
         L.sa_search.argtypes = [vp, vp, i64, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp, sz, vp]
-        for name in ("sa_knn", "sa_knn_ex", "sa_medoid", "sa_prune", "sa_reverse_edges", "sa_repair", "sa_build_graph", "sa_index_create",
+        for name in ("sa_knn", "sa_knn_ex", "sa_quantize", "sa_index_create_q", "sa_medoid", "sa_prune", "sa_reverse_edges", "sa_repair", "sa_build_graph", "sa_index_create",
                      "sa_search"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -196,7 +199,7 @@ def build_graph(base: torch.Tensor, knn_k: int, R: int, prune_mode="rng", do_rep
 
 
 def make_params(sync="adaptive", static_I=0, rho=0.8, staged=True, max_substeps=0, lds_hash_slots=0,
-                ws_hash_slots=0) -> SearchParams:
+                ws_hash_slots=0, rerank=0) -> SearchParams:
     p = SearchParams()
     lib().sa_default_params(C.byref(p))
     p.sync = SYNC[sync] if isinstance(sync, str) else int(sync)
@@ -206,7 +209,23 @@ def make_params(sync="adaptive", static_I=0, rho=0.8, staged=True, max_substeps=
     p.max_substeps = int(max_substeps)
     p.lds_hash_slots = int(lds_hash_slots)
     p.ws_hash_slots = int(ws_hash_slots)
+    p.rerank = int(rerank)
     return p
+
+
+DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
+
+
+def quantize(x: torch.Tensor, dtype: str, stream=None):
+    """Reduced-precision copy of the rows of x: (codes, scales).  Codes are int16 (bf16
+    patterns) or uint8 (fp8 e4m3), rows padded to a multiple of 4 with code 0."""
+    x = pad_dim(_mat(x, "vectors"))
+    n, d = x.shape
+    codes = torch.empty((n, d), dtype=torch.int16 if dtype == "bf16" else torch.uint8, device=x.device)
+    scale = torch.empty(n, dtype=torch.float32, device=x.device)
+    _check(lib().sa_quantize(x.data_ptr(), n, d, x.stride(0), DTYPES[dtype], codes.data_ptr(), codes.stride(0),
+                             scale.data_ptr(), _stream(stream)), "sa_quantize")
+    return codes, scale
 
 
 @dataclass
@@ -226,14 +245,26 @@ class SearchResult:
 class Index:
     """A graph index over device arrays (borrowed: keep vec and adj alive)."""
 
-    def __init__(self, vec: torch.Tensor, adj: torch.Tensor, entry: int, metric="l2"):
+    def __init__(self, vec: torch.Tensor, adj: torch.Tensor, entry: int, metric="l2", dtype="f32", codes=None,
+                 scale=None):
+        """vec: float32 vectors.  dtype "bf16" / "fp8": the search reads codes and scale (from
+        quantize(vec, dtype), made here when not given) and vec serves the re-rank."""
         vec = pad_dim(_mat(vec, "vectors"))
         if adj.dtype != torch.int32 or not adj.is_cuda or not adj.is_contiguous():
             raise SpeedAnnError("adj must be a contiguous int32 device tensor")
-        self.vec, self.adj, self.entry, self.metric = vec, adj, int(entry), metric
+        self.vec, self.adj, self.entry, self.metric, self.dtype = vec, adj, int(entry), metric, dtype
         h = C.c_void_p(0)
-        _check(lib().sa_index_create(vec.data_ptr(), vec.shape[0], vec.shape[1], vec.stride(0), _metric(metric),
-                                     adj.data_ptr(), adj.shape[1], self.entry, C.byref(h)), "sa_index_create")
+        if dtype == "f32":
+            _check(lib().sa_index_create(vec.data_ptr(), vec.shape[0], vec.shape[1], vec.stride(0), _metric(metric),
+                                         adj.data_ptr(), adj.shape[1], self.entry, C.byref(h)), "sa_index_create")
+        else:
+            if codes is None:
+                codes, scale = quantize(vec, dtype)
+            self.codes, self.scale = codes, scale
+            _check(lib().sa_index_create_q(codes.data_ptr(), DTYPES[dtype], scale.data_ptr(), codes.stride(0),
+                                           vec.data_ptr(), vec.stride(0), vec.shape[0], vec.shape[1],
+                                           _metric(metric), adj.data_ptr(), adj.shape[1], self.entry, C.byref(h)),
+                   "sa_index_create_q")
         self._h = h
         self._ws = None
         self._lib = lib()   # kept for __del__, which may run after module teardown

@@ -14,7 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspeedann.so")
-SOURCES = ["capi.hip", "search.hip", "search_single.hip", "search_multi.hip", "knn.hip", "knn_mfma.hip", "graph.hip"]
+SOURCES = ["capi.hip", "search.hip", "search_single_f32.hip", "search_single_bf16.hip", "search_single_fp8.hip",
+           "search_multi_f32.hip", "search_multi_bf16.hip", "search_multi_fp8.hip", "knn.hip", "knn_mfma.hip",
+           "graph.hip", "quant.hip", "rerank.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
@@ -37,7 +39,7 @@ def _compile(src: str) -> str:
 
 def build() -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -69,8 +69,13 @@ static int check_matrix(const void *p, int64_t rows, int32_t d, int64_t ld, cons
 using namespace sa;
 
 struct sa_index {
-    const float *vec;
-    int64_t n, ld;
+    const void *codes;    // stored vectors, rows of ldc elements of dtype
+    const float *scale;   // fp8 scales
+    int64_t ldc;
+    int32_t dtype;
+    const float *vec32;   // float32 vectors for the re-rank (may be null)
+    int64_t ld32;
+    int64_t n;
     int32_t d, metric;
     const int32_t *adj;
     int32_t R, entry;
@@ -212,13 +217,17 @@ int sa_build_graph(const float *base_dev, int64_t n, int32_t d, int64_t ld, int3
     return rc;
 }
 
-int sa_index_create(const float *vec_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, const int32_t *adj_dev,
-                    int32_t R, int32_t entry, sa_index **out)
+int sa_index_create_q(const void *codes_dev, int32_t dtype, const float *scale_dev, int64_t ldc,
+                      const float *vec32_dev, int64_t ld32, int64_t n, int32_t d, int32_t metric,
+                      const int32_t *adj_dev, int32_t R, int32_t entry, sa_index **out)
 {
     int rc;
     if (!out) return set_error(SA_EINVAL, "out is NULL");
     *out = nullptr;
-    if ((rc = check_matrix(vec_dev, n, d, ld, "vectors")) != SA_OK) return rc;
+    if (dtype != SA_F32 && dtype != SA_BF16 && dtype != SA_FP8E4M3) return set_error(SA_EINVAL, "unknown dtype %d", dtype);
+    if ((rc = check_matrix(codes_dev, n, d, ldc, "vectors")) != SA_OK) return rc;
+    if (dtype == SA_FP8E4M3 && !scale_dev) return set_error(SA_EINVAL, "fp8 vectors need their scales");
+    if (vec32_dev && (rc = check_matrix(vec32_dev, n, d, ld32, "float32 vectors")) != SA_OK) return rc;
     if (n < 1 || n >= (int64_t(1) << 31)) return set_error(SA_EINVAL, "n must be in [1, 2^31)");
     if (R < 1 || R > 64) return set_error(SA_EINVAL, "R=%d must be in [1, 64]", R);
     if (entry < 0 || entry >= n) return set_error(SA_EINVAL, "entry %d out of range [0, %lld)", entry, (long long)n);
@@ -226,10 +235,30 @@ int sa_index_create(const float *vec_dev, int64_t n, int32_t d, int64_t ld, int3
     if (!adj_dev) return set_error(SA_EINVAL, "adjacency is NULL");
     sa_index *ix = new (std::nothrow) sa_index;
     if (!ix) return set_error(SA_ENOMEM, "out of host memory");
-    ix->vec = vec_dev; ix->n = n; ix->ld = ld; ix->d = d; ix->metric = metric;
+    ix->codes = codes_dev; ix->scale = scale_dev; ix->ldc = ldc; ix->dtype = dtype;
+    ix->vec32 = vec32_dev; ix->ld32 = vec32_dev ? ld32 : 0;
+    ix->n = n; ix->d = d; ix->metric = metric;
     ix->adj = adj_dev; ix->R = R; ix->entry = entry;
     *out = ix;
     return SA_OK;
+}
+
+int sa_index_create(const float *vec_dev, int64_t n, int32_t d, int64_t ld, int32_t metric, const int32_t *adj_dev,
+                    int32_t R, int32_t entry, sa_index **out)
+{
+    return sa_index_create_q(vec_dev, SA_F32, nullptr, ld, vec_dev, ld, n, d, metric, adj_dev, R, entry, out);
+}
+
+int sa_quantize(const float *x_dev, int64_t n, int32_t d, int64_t ld, int32_t dtype, void *codes_dev, int64_t ldc,
+                float *scale_dev, void *hip_stream)
+{
+    int rc;
+    if (dtype != SA_BF16 && dtype != SA_FP8E4M3) return set_error(SA_EINVAL, "dtype %d: quantize to bf16 or fp8", dtype);
+    if ((rc = check_matrix(x_dev, n, d, ld, "vectors")) != SA_OK) return rc;
+    if ((rc = check_matrix(codes_dev, n, d, ldc, "codes")) != SA_OK) return rc;
+    if (n > 0 && !scale_dev) return set_error(SA_EINVAL, "scale is NULL");
+    if ((rc = check_device()) != SA_OK) return rc;
+    return launch_quantize(x_dev, n, d, ld, dtype, codes_dev, ldc, scale_dev, (hipStream_t)hip_stream);
 }
 
 void sa_index_destroy(sa_index *index) { delete index; }
@@ -243,6 +272,8 @@ static int check_search(const sa_index *ix, int64_t nq, int32_t k, int32_t L, in
     if (p.sync < SA_SYNC_BSP || p.sync > SA_SYNC_ADAPTIVE) return set_error(SA_EINVAL, "unknown sync %d", p.sync);
     if (!(p.rho >= 0.0f) || !std::isfinite(p.rho)) return set_error(SA_EINVAL, "rho must be finite and >= 0");
     if (p.max_substeps < 0) return set_error(SA_EINVAL, "max_substeps must be >= 0");
+    if (p.rerank < -1) return set_error(SA_EINVAL, "rerank=%d must be -1, 0 or positive", p.rerank);
+    if (p.rerank != 0 && !ix->vec32) return set_error(SA_EINVAL, "re-rank needs the index's float32 vectors");
     return SA_OK;
 }
 
@@ -269,7 +300,9 @@ int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64
     if (nq > 0 && (!ids_dev || !dists_dev)) return set_error(SA_EINVAL, "output is NULL");
     if ((rc = check_device()) != SA_OK) return rc;
     SearchLaunch a;
-    a.vec = index->vec; a.ld = index->ld; a.n = index->n; a.d = index->d; a.metric = index->metric;
+    a.codes = index->codes; a.scale = index->scale; a.ldc = index->ldc; a.dtype = index->dtype;
+    a.vec32 = index->vec32; a.ld32 = index->ld32;
+    a.n = index->n; a.d = index->d; a.metric = index->metric;
     a.adj = index->adj; a.R = index->R; a.entry = index->entry;
     a.queries = queries_dev; a.ldq = ldq; a.nq = nq; a.k = k; a.L = L; a.M = M; a.p = p;
     a.ids = ids_dev; a.dists = dists_dev; a.stats = stats_dev; a.workspace = workspace; a.ws_bytes = ws_bytes;

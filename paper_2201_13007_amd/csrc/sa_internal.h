@@ -65,8 +65,12 @@ int launch_knn_scan(const float *base, int64_t n, int32_t d, int64_t ld, const f
                     hipStream_t stream);
 
 struct SearchLaunch {
-    const float *vec;
-    int64_t ld, n;
+    const void *codes;     // stored vectors (float32, bf16 or fp8 codes), rows of ldc elements
+    const float *scale;    // fp8 scales
+    int64_t ldc;
+    int32_t dtype;
+    const float *vec32;    // float32 vectors for the re-rank (may be null)
+    int64_t ld32, n;
     int32_t d, metric;
     const int32_t *adj;
     int32_t R, entry;
@@ -80,6 +84,9 @@ struct SearchLaunch {
     void *workspace;
     size_t ws_bytes;
 };
+
+int launch_quantize(const float *x, int64_t n, int32_t d, int64_t ld, int32_t dtype, void *codes, int64_t ldc,
+                    float *scale, hipStream_t stream);
 
 size_t search_workspace_bytes(int64_t nq, int32_t L, int32_t M, const sa_search_params &p, int32_t R);
 int launch_search(const SearchLaunch &a, hipStream_t stream);

@@ -1,6 +1,6 @@
 // Host side of the search: parameter resolution, LDS layout, workspace sizing and the
-// launch of the single-worker kernel (search_single.hip) or of the general kernel
-// (search_multi.hip, whose body is in search_body.h).
+// launch of the single-worker kernel (search_single.h) or of the general kernel
+// (search_multi.h, whose body is in search_body.h), one instantiation per storage type.
 #include "search_body.h"
 
 #include <algorithm>
@@ -76,6 +76,9 @@ void resolve_params(const sa_search_params &in, int L, int M, int R, int &llog2,
         // local step may add on top.
         int64_t want = (compact_table(M, llog2) ? 32ll : 64ll) * L + 8ll * M * R;
         if (want < 4096) want = 4096;
+        // a re-rank takes the last 1025 entries of the slot list, beyond the three
+        // quarters the search may fill: at least 8192 slots
+        if (in.rerank != 0 && want < 8192) want = 8192;
         glog2 = ilog2_exact(want);
     }
 }
@@ -98,6 +101,7 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     if (llog2 != 0 && (llog2 < 6 || llog2 > 14))
         return set_error(SA_EINVAL, "lds_hash_slots must be a power of two in [64, 16384] (or -1 for none)");
     if (glog2 < 6 || glog2 > 26) return set_error(SA_EINVAL, "ws_hash_slots must be a power of two in [64, 2^26]");
+    if (a.p.rerank != 0 && glog2 < 13) return set_error(SA_EINVAL, "a re-rank needs ws_hash_slots >= 8192");
     if (llog2 > 0 && (int64_t(1) << llog2) / 2 < (int64_t)a.M * a.R + 1)
         return set_error(SA_EINVAL, "lds_hash_slots too small for M * R new vertices per local step");
     if ((int64_t(1) << glog2) * 3 / 4 < (int64_t)a.M * a.R + 1)
@@ -112,7 +116,8 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
         return set_error(SA_ECAPACITY, "L=%d, M=%d need %u bytes of LDS per query (limit 163840); lower L, M or "
                          "lds_hash_slots", a.L, a.M, Y.total);
     KArgs A;
-    A.vec = a.vec; A.ld = a.ld; A.adj = a.adj; A.queries = a.queries; A.ldq = a.ldq;
+    A.codes = a.codes; A.scale = a.scale; A.ldc = a.ldc; A.vec32 = a.vec32; A.ld32 = a.ld32; A.rerank = a.p.rerank;
+    A.adj = a.adj; A.queries = a.queries; A.ldq = a.ldq;
     A.ids = a.ids; A.dists = a.dists; A.stats = a.stats;
     A.ghash = reinterpret_cast<unsigned long long *>(a.workspace);
     A.n = a.n;
@@ -124,8 +129,23 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     A.o_hash = Y.o_hash; A.o_q = Y.o_q;
     if (a.nq == 0) return SA_OK;
     if (a.d > 1024) return set_error(SA_EUNSUPPORTED, "d=%d exceeds 1024", a.d);
-    if (compact_table(a.M, llog2)) return launch_search_single(A, a.nq, stream);
-    return launch_search_multi(A, a.nq, a.M, Y.total, stream);
+    int rc;
+    const bool compact = compact_table(a.M, llog2);
+    if (compact) {
+        if (a.dtype == SA_BF16) rc = launch_search_single_bf16(A, a.nq, stream);
+        else if (a.dtype == SA_FP8E4M3) rc = launch_search_single_fp8(A, a.nq, stream);
+        else rc = launch_search_single_f32(A, a.nq, stream);
+    } else {
+        if (a.dtype == SA_BF16) rc = launch_search_multi_bf16(A, a.nq, a.M, Y.total, stream);
+        else if (a.dtype == SA_FP8E4M3) rc = launch_search_multi_fp8(A, a.nq, a.M, Y.total, stream);
+        else rc = launch_search_multi_f32(A, a.nq, a.M, Y.total, stream);
+    }
+    if (rc != SA_OK || a.p.rerank == 0) return rc;
+    // the list sits at the end of the slot list, which follows the table in each region
+    const int64_t stride = (int64_t)bytes_per_slot(a.M, llog2) << glog2;
+    const int64_t list_off = ((int64_t)(compact ? 4 : 8) << glog2) + 4 * ((int64_t(1) << glog2) - 1025);
+    return launch_rerank(a.vec32, a.ld32, a.queries, a.ldq, a.nq, a.d, a.metric, a.k, a.L, a.workspace, stride,
+                         list_off, a.ids, a.dists, stream);
 }
 
 }  // namespace sa

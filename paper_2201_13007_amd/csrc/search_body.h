@@ -60,8 +60,12 @@ struct Ctrl {
 };
 
 struct KArgs {
-    const float *vec;
-    int64_t ld;
+    const void *codes;           // stored vectors: rows of ldc elements of the index's dtype
+    const float *scale;          // fp8: one scale per vector
+    int64_t ldc;
+    const float *vec32;          // float32 vectors for the re-rank
+    int64_t ld32;
+    int32_t rerank;
     const int32_t *adj;
     const float *queries;
     int64_t ldq;
@@ -188,17 +192,54 @@ __host__ __device__ inline int lanes_per_vector(int d)
     return lpv;
 }
 
-// Keys of the vectors ids[0..n) to out[0..n); qs is the query, zero padded to 16 LPV
-// floats.  Every load is issued unconditionally (from a clamped address, its value
-// dropped afterwards): loads under a lane condition each get their own wait, which would
-// turn one memory round trip into four.
-template <int LPV, bool L2>
-__device__ __forceinline__ void distances(const KArgs &A, const float *qs, const int32_t *ids, int n, uint64_t *out)
+// Where a kernel reads vectors: rows of ld elements of storage type DT (sa_dtype).
+struct VecSrc {
+    const void *p;
+    const float *scale;   // SA_FP8E4M3 only
+    int64_t ld;
+};
+
+// value of an e4m3 code (finite variant: bias 7, 3 mantissa bits, subnormals m * 2^-9)
+__device__ __forceinline__ float e4m3_value(uint32_t c)
+{
+    const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+    const float sub = (float)m * 0.001953125f;
+    const float nrm = __uint_as_float(((e + 120u) << 23) | (m << 20));
+    const float v = e == 0u ? sub : nrm;
+    return (c & 0x80u) ? -v : v;
+}
+
+// coordinates 4c .. 4c+3 of row id as the float32 values they stand for
+template <int DT>
+__device__ __forceinline__ float4 load4(const VecSrc &V, int32_t id, int c)
+{
+    if constexpr (DT == SA_F32) {
+        return *reinterpret_cast<const float4 *>(static_cast<const float *>(V.p) + (int64_t)id * V.ld + 4 * c);
+    } else if constexpr (DT == SA_BF16) {
+        const uint2 w = *(reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(V.p) + (int64_t)id * V.ld) + c);
+        return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u), __uint_as_float(w.y << 16),
+                           __uint_as_float(w.y & 0xFFFF0000u));
+    } else {
+        const uint32_t w = *(reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(V.p) + (int64_t)id * V.ld) + c);
+        const float s = V.scale[id];
+        return make_float4(s * e4m3_value(w & 0xFFu), s * e4m3_value((w >> 8) & 0xFFu),
+                           s * e4m3_value((w >> 16) & 0xFFu), s * e4m3_value(w >> 24));
+    }
+}
+
+// Keys of the vectors ids[0..n) (n <= 64) to out[0..n), 64 / LPV vectors per pass; qs is
+// the query, zero padded to 16 LPV floats.  The loads are issued unconditionally, from
+// clamped addresses (a dropped id reads row 0): loads under lane conditions each get their
+// own wait, which would turn one memory round trip into four.  (Written as a pass loop
+// over arrays: the same steps as a per-vector helper cost some twenty more registers.)
+template <int LPV, bool L2, int DT>
+__device__ __forceinline__ void distances(const VecSrc &V, int d, const float *qs, const int32_t *ids, int n,
+                                          uint64_t *out)
 {
     constexpr int VPW = 64 / LPV;
-    const int lane = __lane_id(), grp = lane / LPV, g = lane % LPV;
-    const int nch = A.d >> 2;
     constexpr int PB = 1;   // more vectors in flight cost two registers each (d = 128)
+    const int lane = __lane_id(), grp = lane / LPV, g = lane % LPV;
+    const int nch = d >> 2;
     for (int p0 = 0; p0 < n; p0 += VPW * PB) {
         float4 x[PB][4];
         int32_t id[PB];
@@ -207,11 +248,11 @@ __device__ __forceinline__ void distances(const KArgs &A, const float *qs, const
             const int idx = p0 + pp * VPW + grp;
             const int32_t raw = ids[idx & 63];
             id[pp] = idx < n ? raw : -1;
-            const float *row = A.vec + (int64_t)(id[pp] < 0 ? 0 : id[pp]) * A.ld;
+            const int32_t row = id[pp] < 0 ? 0 : id[pp];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int c = g + LPV * i;
-                x[pp][i] = *reinterpret_cast<const float4 *>(row + 4 * (c < nch ? c : 0));
+                x[pp][i] = load4<DT>(V, row, c < nch ? c : 0);
             }
         }
 #pragma unroll
@@ -237,6 +278,14 @@ __device__ __forceinline__ void distances(const KArgs &A, const float *qs, const
             if (g == LPV - 1 && idx < n) out[idx] = make_key(L2 ? (float)acc : (float)(-acc), id[pp]);
         }
     }
+}
+
+// Where a query leaves its final list for the re-rank: the last 1025 entries of its slot
+// list (a count, then up to 1024 ids).  Slots stop at three quarters of a table of at
+// least 4096, so the search never writes there; the re-rank zeroes it again.
+__device__ __forceinline__ int32_t *rerank_list(uint32_t *slots, int glog2)
+{
+    return reinterpret_cast<int32_t *>(slots + (1u << glog2) - 1025u);
 }
 
 // ---------------------------------------------------------------- register queue
@@ -397,7 +446,7 @@ __device__ void migrate_table(const unsigned long long *lh, int llog2, unsigned 
     }
 }
 
-template <int LPV, int NI>
+template <int LPV, int NI, int DT>
 __device__ __forceinline__ void search_body(const KArgs &A)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -443,6 +492,7 @@ __device__ __forceinline__ void search_body(const KArgs &A)
                 c < nch ? *reinterpret_cast<const float4 *>(qrow + 4 * c) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     const bool l2 = A.metric == SA_L2;
+    const VecSrc V{A.codes, A.scale, A.ldc};
     const int32_t n = (int32_t)A.n;
     // this lane's entry of an adjacency row (R <= 64); lanes past R load entry 0 and drop it
     const int32_t *const adj_lane = A.adj + (lane < R ? lane : 0);
@@ -458,8 +508,8 @@ __device__ __forceinline__ void search_body(const KArgs &A)
     if (w == 0) {
         if (lane == 0) claim[0] = A.entry;
         __builtin_amdgcn_wave_barrier();
-        if (l2) distances<LPV, true>(A, qs, claim, 1, nkey);
-        else distances<LPV, false>(A, qs, claim, 1, nkey);
+        if (l2) distances<LPV, true, DT>(V, A.d, qs, claim, 1, nkey);
+        else distances<LPV, false, DT>(V, A.d, qs, claim, 1, nkey);
         __builtin_amdgcn_wave_barrier();
         const uint64_t k0 = nkey[0];
         bool fresh = false;
@@ -535,8 +585,8 @@ __device__ __forceinline__ void search_body(const KArgs &A)
                     hcount += nclaim;
                     if (fresh) claim[__popcll(cm & lanemask_lt())] = u;
                     __builtin_amdgcn_wave_barrier();
-                    if (l2) distances<LPV, true>(A, qs, claim, nclaim, nkey);
-                    else distances<LPV, false>(A, qs, claim, nclaim, nkey);
+                    if (l2) distances<LPV, true, DT>(V, A.d, qs, claim, nclaim, nkey);
+                    else distances<LPV, false, DT>(V, A.d, qs, claim, nclaim, nkey);
                     __builtin_amdgcn_wave_barrier();
                     const uint64_t mk = lane < nclaim ? nkey[lane] : KEY_EMPTY;
                     __builtin_amdgcn_wave_barrier();
@@ -704,8 +754,8 @@ __device__ __forceinline__ void search_body(const KArgs &A)
                     const int nclaim = __popcll(cm);
                     if (claimed) claim[__popcll(cm & lanemask_lt())] = u;
                     __builtin_amdgcn_wave_barrier();
-                    if (l2) distances<LPV, true>(A, qs, claim, nclaim, nkey);
-                    else distances<LPV, false>(A, qs, claim, nclaim, nkey);
+                    if (l2) distances<LPV, true, DT>(V, A.d, qs, claim, nclaim, nkey);
+                    else distances<LPV, false, DT>(V, A.d, qs, claim, nclaim, nkey);
                     __builtin_amdgcn_wave_barrier();
                     const uint64_t mk = lane < nclaim ? nkey[lane] : KEY_EMPTY;
                     __builtin_amdgcn_wave_barrier();
@@ -868,7 +918,22 @@ __device__ __forceinline__ void search_body(const KArgs &A)
     {
         const bool from_regs = C->done != 0;   // the search ended in wavefront 0's queue
         const int slen = C->slen;
-        if (from_regs) {
+        if (A.rerank != 0) {
+            // hand the first nr entries of the final list to the re-rank kernel
+            const int nr = A.rerank < 0 ? slen : min(A.rerank, slen);
+            int32_t *const list = rerank_list(reinterpret_cast<uint32_t *>(gslots), glog2);
+            if (from_regs) {
+                if (w == 0) {
+#pragma unroll
+                    for (int i = 0; i < NI; ++i)
+                        if (64 * i + lane < nr) list[1 + 64 * i + lane] = key_id(ls.k[i]);
+                }
+            } else {
+                const uint64_t *S = skey_base + sb * L;
+                for (int i = tid; i < nr; i += nthr) list[1 + i] = key_id(S[i]);
+            }
+            if (tid == 0) list[0] = nr;
+        } else if (from_regs) {
             if (w == 0) {
 #pragma unroll
                 for (int i = 0; i < NI; ++i) {
@@ -916,7 +981,14 @@ __device__ __forceinline__ void search_body(const KArgs &A)
 
 }  // namespace search_detail
 
-int launch_search_single(const search_detail::KArgs &A, int64_t nq, hipStream_t s);
-int launch_search_multi(const search_detail::KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s);
+int launch_rerank(const float *vec32, int64_t ld32, const float *queries, int64_t ldq, int64_t nq, int32_t d,
+                  int32_t metric, int32_t k, int32_t L, void *ws, int64_t stride, int64_t list_off, int32_t *ids,
+                  float *dists, hipStream_t s);
+int launch_search_single_f32(const search_detail::KArgs &A, int64_t nq, hipStream_t s);
+int launch_search_single_bf16(const search_detail::KArgs &A, int64_t nq, hipStream_t s);
+int launch_search_single_fp8(const search_detail::KArgs &A, int64_t nq, hipStream_t s);
+int launch_search_multi_f32(const search_detail::KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s);
+int launch_search_multi_bf16(const search_detail::KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s);
+int launch_search_multi_fp8(const search_detail::KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s);
 
 }  // namespace sa

@@ -1,0 +1,57 @@
+// The general search kernel, one wavefront per worker (see search_body.h): every case
+// with two or more workers, and one worker with an LDS visited table.
+#pragma once
+#include "search_body.h"
+
+namespace sa {
+namespace search_detail {
+
+template <int LPV, int NI, int DT>
+__global__ void __launch_bounds__(1024) search_multi(KArgs A)
+{
+    search_body<LPV, NI, DT>(A);
+}
+
+template <int LPV, int NI, int DT>
+hipError_t launch1(const KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s)
+{
+    auto k = search_multi<LPV, NI, DT>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64 * M), lds, s, A);
+    return hipGetLastError();
+}
+
+template <int LPV, int DT>
+hipError_t launch1_ni(const KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s)
+{
+    const int ni = (A.L + 63) / 64;
+    if (ni <= 1) return launch1<LPV, 1, DT>(A, nq, M, lds, s);
+    if (ni <= 2) return launch1<LPV, 2, DT>(A, nq, M, lds, s);
+    if (ni <= 4) return launch1<LPV, 4, DT>(A, nq, M, lds, s);
+    if (ni <= 6) return launch1<LPV, 6, DT>(A, nq, M, lds, s);
+    if (ni <= 8) return launch1<LPV, 8, DT>(A, nq, M, lds, s);
+    return launch1<LPV, 16, DT>(A, nq, M, lds, s);
+}
+
+// one instantiation per storage type, each in a file of its own (search_multi_*.hip)
+template <int DT>
+int launch_dt(const KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s)
+{
+    hipError_t e;
+    switch (lanes_per_vector(A.d)) {
+    case 1: e = launch1_ni<1, DT>(A, nq, M, lds, s); break;
+    case 2: e = launch1_ni<2, DT>(A, nq, M, lds, s); break;
+    case 4: e = launch1_ni<4, DT>(A, nq, M, lds, s); break;
+    case 8: e = launch1_ni<8, DT>(A, nq, M, lds, s); break;
+    case 16: e = launch1_ni<16, DT>(A, nq, M, lds, s); break;
+    case 32: e = launch1_ni<32, DT>(A, nq, M, lds, s); break;
+    default: e = launch1_ni<64, DT>(A, nq, M, lds, s); break;
+    }
+    if (e != hipSuccess) return hip_fail(e, "search kernel launch");
+    return SA_OK;
+}
+
+}  // namespace search_detail
+}  // namespace sa

@@ -20,6 +20,7 @@
 // Distances.  LPV lanes share one vector, each lane four float4 chunks (c = g, g + LPV,
 // ...), accumulated in double precision, summed into the group's last lane by DPP row
 // shifts and broadcasts, and rounded once to float.  The query row sits in LDS.
+#pragma once
 #include "search_body.h"
 
 namespace sa {
@@ -27,8 +28,10 @@ namespace single_detail {
 
 using search_detail::KArgs;
 using search_detail::NO_SLOT;
+using search_detail::VecSrc;
 using search_detail::bpermute64;
 using search_detail::distances;
+using search_detail::rerank_list;
 using search_detail::hash_slot;
 using search_detail::lanemask_lt;
 using search_detail::low_bits;
@@ -165,7 +168,7 @@ __device__ __forceinline__ uint32_t claim(uint32_t *T, int log2cap, uint32_t u, 
     return NO_SLOT;
 }
 
-template <int LPV, int NI, bool L2>
+template <int LPV, int NI, bool L2, int DT>
 __global__ void __launch_bounds__(64) search_single(KArgs A)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -180,6 +183,7 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
     uint32_t *const tbl = reinterpret_cast<uint32_t *>(A.ghash) + ((size_t)qi << (g2 + 1));
     uint32_t *const slots = tbl + (1u << g2);
     const int cap = (3 << g2) / 4;
+    const VecSrc V{A.codes, A.scale, A.ldc};
 
     {
         const int nch = A.d >> 2;
@@ -202,7 +206,7 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
         Q.chk[i] = 0;
     }
     // dist(P, Q); P goes into the queue and the visited set
-    distances<LPV, L2>(A, qs, sid, 1, nkey);
+    distances<LPV, L2, DT>(V, A.d, qs, sid, 1, nkey);
     __builtin_amdgcn_wave_barrier();
     {
         const uint64_t k0 = nkey[0];
@@ -253,7 +257,7 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
             }
             nslot += nnew;
             __builtin_amdgcn_wave_barrier();
-            distances<LPV, L2>(A, qs, sid, nnew, nkey);
+            distances<LPV, L2, DT>(V, A.d, qs, sid, nnew, nkey);
             __builtin_amdgcn_wave_barrier();
             const uint64_t mk = lane < nnew ? nkey[lane] : KEY_EMPTY;
             __builtin_amdgcn_wave_barrier();
@@ -276,13 +280,23 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
         merges++;   // the queue is S unchanged
     }
 
+    if (A.rerank != 0) {
+        // hand the first nr entries of the final list to the re-rank kernel
+        const int nr = A.rerank < 0 ? Q.len : min(A.rerank, Q.len);
+        int32_t *const list = rerank_list(slots, g2);
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        const int p = 64 * i + lane;
-        if (p < A.k) {
-            const bool ok = p < Q.len;
-            A.ids[qi * A.k + p] = ok ? key_id(Q.k[i]) : -1;
-            A.dists[qi * A.k + p] = ok ? key_dist(Q.k[i]) : __builtin_inff();
+        for (int i = 0; i < NI; ++i)
+            if (64 * i + lane < nr) list[1 + 64 * i + lane] = key_id(Q.k[i]);
+        if (lane == 0) list[0] = nr;
+    } else {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int p = 64 * i + lane;
+            if (p < A.k) {
+                const bool ok = p < Q.len;
+                A.ids[qi * A.k + p] = ok ? key_id(Q.k[i]) : -1;
+                A.dists[qi * A.k + p] = ok ? key_dist(Q.k[i]) : __builtin_inff();
+            }
         }
     }
     // leave the workspace zero-filled for the next launch
@@ -304,44 +318,44 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
     }
 }
 
-template <int LPV, int NI>
+template <int LPV, int NI, int DT>
 hipError_t launch1(const KArgs &A, int64_t nq, hipStream_t s)
 {
-    auto k = A.metric == SA_L2 ? search_single<LPV, NI, true> : search_single<LPV, NI, false>;
+    auto k = A.metric == SA_L2 ? search_single<LPV, NI, true, DT> : search_single<LPV, NI, false, DT>;
     const uint32_t lds = 64 * 8 + 64 * 4 + 64 * LPV;
     hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64), lds, s, A);
     return hipGetLastError();
 }
 
-template <int LPV>
+template <int LPV, int DT>
 hipError_t launch1_ni(const KArgs &A, int64_t nq, hipStream_t s)
 {
     const int ni = (A.L + 63) / 64;
-    if (ni <= 1) return launch1<LPV, 1>(A, nq, s);
-    if (ni <= 2) return launch1<LPV, 2>(A, nq, s);
-    if (ni <= 4) return launch1<LPV, 4>(A, nq, s);
-    if (ni <= 6) return launch1<LPV, 6>(A, nq, s);
-    if (ni <= 8) return launch1<LPV, 8>(A, nq, s);
-    return launch1<LPV, 16>(A, nq, s);
+    if (ni <= 1) return launch1<LPV, 1, DT>(A, nq, s);
+    if (ni <= 2) return launch1<LPV, 2, DT>(A, nq, s);
+    if (ni <= 4) return launch1<LPV, 4, DT>(A, nq, s);
+    if (ni <= 6) return launch1<LPV, 6, DT>(A, nq, s);
+    if (ni <= 8) return launch1<LPV, 8, DT>(A, nq, s);
+    return launch1<LPV, 16, DT>(A, nq, s);
 }
 
-}  // namespace single_detail
-
-int launch_search_single(const search_detail::KArgs &A, int64_t nq, hipStream_t s)
+// one instantiation per storage type, each in a file of its own (search_single_*.hip)
+template <int DT>
+int launch_dt(const KArgs &A, int64_t nq, hipStream_t s)
 {
-    using namespace single_detail;
     hipError_t e;
     switch (search_detail::lanes_per_vector(A.d)) {
-    case 1: e = launch1_ni<1>(A, nq, s); break;
-    case 2: e = launch1_ni<2>(A, nq, s); break;
-    case 4: e = launch1_ni<4>(A, nq, s); break;
-    case 8: e = launch1_ni<8>(A, nq, s); break;
-    case 16: e = launch1_ni<16>(A, nq, s); break;
-    case 32: e = launch1_ni<32>(A, nq, s); break;
-    default: e = launch1_ni<64>(A, nq, s); break;
+    case 1: e = launch1_ni<1, DT>(A, nq, s); break;
+    case 2: e = launch1_ni<2, DT>(A, nq, s); break;
+    case 4: e = launch1_ni<4, DT>(A, nq, s); break;
+    case 8: e = launch1_ni<8, DT>(A, nq, s); break;
+    case 16: e = launch1_ni<16, DT>(A, nq, s); break;
+    case 32: e = launch1_ni<32, DT>(A, nq, s); break;
+    default: e = launch1_ni<64, DT>(A, nq, s); break;
     }
     if (e != hipSuccess) return hip_fail(e, "search kernel launch");
     return SA_OK;
 }
 
+}  // namespace single_detail
 }  // namespace sa

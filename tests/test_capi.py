@@ -76,6 +76,20 @@ def test_validation_errors_without_device(B):
     used = C.c_int32(7)
     assert L.sa_knn_ex(fake, 10, 32, 32, fake, 3, 32, 5, 0, 0, fake, fake, 3, C.byref(used), None) == -1
     assert "path" in _err(B) and used.value == 0
+    # reduced precision: bad dtype, fp8 without scales, re-rank without float32 vectors
+    assert L.sa_quantize(fake, 10, 32, 32, 0, fake, 32, fake, None) == -1
+    assert "dtype" in _err(B)
+    h = C.c_void_p(0)
+    assert L.sa_index_create_q(fake, 2, None, 32, None, 32, 10, 32, 0, fake, 16, 0, C.byref(h)) == -1
+    assert "scale" in _err(B)
+    assert L.sa_index_create_q(fake, 1, None, 32, None, 32, 10, 32, 0, fake, 16, 0, C.byref(h)) == 0
+    pr = B.SearchParams()
+    L.sa_default_params(C.byref(pr))
+    assert pr.rerank == 0
+    pr.rerank = -1
+    assert L.sa_search(h, fake, 4, 32, 10, 64, 1, C.byref(pr), fake, fake, None, fake, 1 << 30, None) == -1
+    assert "float32 vectors" in _err(B)
+    L.sa_index_destroy(h)
     assert L.sa_prune(fake, 10, 32, 32, 0, fake, 65, 16, 1, fake, None) == -1
     e = C.c_int32(0)
     assert L.sa_build_graph(fake, 1, 32, 32, 0, 16, 16, 0, 0, 1, 4, 4, fake, C.byref(e), None, None, None) == -1
