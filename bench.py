@@ -8,6 +8,13 @@ neighbourhood pruning to R = 32, connectivity repair, medoid entry), exact groun
 on the GPU, and the operating point: for each walker count M the smallest L of the sweep
 whose mean recall@10 reaches 0.99; the point with the highest QPS is timed.
 
+With --workload deep: the DEEP-shaped 1M x 96 inner-product workload (512-component
+mixture with per-coordinate variance 1/i, scaled to unit norm) searched over float32, bf16 and fp8-e4m3 vector storage,
+with and without the exact float32 re-rank of the final list.  Each form is timed at its
+own operating point (smallest swept L reaching recall@10 0.99) and compared with the
+float32 path at equal L: recall, QPS and the error of the returned distances against
+FP64.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -67,6 +74,167 @@ def load_traffic(workload_key):
     return t
 
 
+def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors"):
+    """The oracle's search timed on the host cores over a growing prefix of the queries
+    until about `seconds` of CPU work."""
+    import oracle
+    adj_h = adj.cpu().numpy()
+    nq = w.queries.shape[0]
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    done, t_cpu, bs = 0, 0.0, 64
+    while t_cpu < seconds and done < nq:
+        n1 = min(bs, nq - done)
+        s0 = time.perf_counter()
+        oracle.speedann(w.base, adj_h, entry, w.queries[done:done + n1], k, L, M, sync="adaptive", rho=0.8,
+                        staged=True, metric=w.metric)
+        t_cpu += time.perf_counter() - s0
+        done += n1
+        bs = min(bs * 2, 2048)
+    cpu = {"value": round(done / t_cpu, 1), "unit": "queries/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"first {done} of the {nq} queries, same graph, {storage}, M={M}, L={L}, adaptive rho 0.8 "
+                     f"staged, lockstep emulation of Algorithm 3 in plain C, one query per OpenMP thread"}
+    log(f"cpu oracle: {cpu['value']} q/s on {nthreads} threads ({done} queries, {t_cpu:.1f}s)")
+    return cpu
+
+
+def timed_launches(torch, fn, reps):
+    """Per-launch device times (ms) of fn() on torch's current stream, which is the stream
+    the search runs on."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in evs])
+
+
+STORAGE_BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
+
+
+def deep_main(args, torch, B, synth, dev):
+    t0 = time.time()
+    w = synth.deep_like(n=args.n, nq=args.nq)
+    log(f"data {w.name}: {w.base.shape} + {w.queries.shape} queries in {time.time() - t0:.1f}s")
+    base = torch.from_numpy(w.base).to(dev)
+    queries = torch.from_numpy(w.queries).to(dev)
+    k, d, R = w.k, w.base.shape[1], w.graph_R
+    nq = args.nq
+
+    t0 = time.time()
+    adj, entry, ginfo = B.build_graph(base, w.graph_knn, R, w.graph_prune, w.graph_repair, keep_local=1,
+                                      metric=w.metric)
+    torch.cuda.synchronize()
+    t_graph = time.time() - t0
+    log(f"graph built in {t_graph:.1f}s: entry {entry}, {ginfo}")
+    t0 = time.time()
+    gt, _ = B.knn(base, queries, k, metric=w.metric)
+    torch.cuda.synchronize()
+    log(f"ground truth in {time.time() - t0:.2f}s")
+
+    M = args.M or 1
+    forms = [("f32", 0), ("bf16", 0), ("bf16", -1), ("fp8", 0), ("fp8", -1)]
+    index = {s: B.Index(base, adj, entry, metric=w.metric, dtype=s) for s in ("f32", "bf16", "fp8")}
+    base64 = w.base.astype(np.float64)
+    q64 = w.queries.astype(np.float64)
+
+    def run(storage, rr, L, stats=False, out=None):
+        p = B.make_params(sync="adaptive", rho=0.8, staged=True, rerank=rr)
+        return index[storage].search(queries, k, L, M, params=p, stats=stats, out=out)
+
+    def measure(storage, rr, L, reps):
+        r = run(storage, rr, L, stats=True)
+        ids = r.ids
+        rec = recall_at_k(ids, gt, k).mean().item()
+        out = (torch.empty_like(r.ids), torch.empty_like(r.dists), None)
+        run(storage, rr, L, out=out)
+        ms = timed_launches(torch, lambda: run(storage, rr, L, out=out), reps)
+        # returned distances against FP64 inner products of the same (query, id) pairs
+        ih, dh = ids.cpu().numpy(), r.dists.cpu().numpy().astype(np.float64)
+        ok = ih >= 0
+        exact = -np.einsum("qd,qkd->qk", q64, base64[np.where(ok, ih, 0)])
+        err = np.abs(dh - exact)[ok]
+        st = r.stats.cpu().numpy()
+        return {"storage": storage, "rerank": "whole list" if rr < 0 else "none", "L": L,
+                "recall": round(rec, 5), "ms": round(float(np.median(ms)), 4),
+                "qps": round(nq / float(np.median(ms)) * 1e3),
+                "dist_err_max": float(f"{err.max():.3e}"), "dist_err_mean": float(f"{err.mean():.3e}"),
+                "dist_comps": round(float(st[:, 3].mean()), 1), "expansions": round(float(st[:, 2].mean()), 1),
+                "flagged": int(((st[:, 5] & 3) != 0).sum())}, st, ms
+
+    # each form's operating point
+    points, at_f32 = [], []
+    for storage, rr in forms:
+        hit = None
+        for L in ([args.L] if args.L else L_SWEEP):
+            row, _, _ = measure(storage, rr, L, 3)
+            log(f"{storage:4s} rerank={row['rerank']:10s} L={L:4d} recall={row['recall']:.4f} "
+                f"qps={row['qps']:>9} err max {row['dist_err_max']:.2e} mean {row['dist_err_mean']:.2e}")
+            if row["recall"] >= TARGET:
+                hit = row
+                break
+        points.append(hit if hit else row)
+    L32 = points[0]["L"]
+    for storage, rr in forms:
+        row, _, _ = measure(storage, rr, L32, 3)
+        at_f32.append(row)
+
+    # the fastest form at the target is timed over the full step count
+    ok_points = [p for p in points if p["recall"] >= TARGET]
+    best = max(ok_points, key=lambda p: p["qps"]) if ok_points else max(points, key=lambda p: p["recall"])
+    storage, rr, L = best["storage"], (-1 if best["rerank"] != "none" else 0), best["L"]
+    row, stats, _ = measure(storage, rr, L, 1)
+    out = (torch.empty((nq, k), dtype=torch.int32, device=dev), torch.empty((nq, k), dtype=torch.float32, device=dev),
+           None)
+    for _ in range(args.warmup):
+        run(storage, rr, L, out=out)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    launch_ms = timed_launches(torch, lambda: run(storage, rr, L, out=out), args.steps)
+    wall = time.perf_counter() - t_start
+    ms_per_step = wall * 1e3 / args.steps
+    qps = nq / (ms_per_step / 1e3)
+    log(f"timed {storage} rerank={best['rerank']} M={M} L={L}: {ms_per_step:.3f} ms/step, QPS {qps:,.0f}")
+
+    # algorithmic bytes of the search: per distance one stored row (+ its fp8 scale), per
+    # expansion one adjacency row, the query, and (re-rank) the float32 rows of the list
+    D = stats[:, 3].astype(np.float64)
+    E = stats[:, 2].astype(np.float64)
+    row_bytes = d * STORAGE_BYTES[storage] + (4 if storage == "fp8" else 0)
+    bytes_launch = float((D * row_bytes + E * R * 4 + d * 4 + k * 8).sum())
+    if rr:
+        bytes_launch += float(nq * L * (d * 4 + 4))
+    achieved = bytes_launch / (launch_ms.mean() / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "algorithmic_bytes_per_launch": round(bytes_launch),
+                "kernel_ms": round(float(launch_ms.mean()), 4),
+                "note": "search and re-rank launches timed together" if rr else "search launch"}
+    cpu = None if args.no_cpu else cpu_oracle(w, adj, entry, k, L32, M, args.cpu_seconds)
+    res = {
+        "metric": "QPS and recall@10 by vector storage (fp32 / bf16 / fp8-e4m3, exact fp32 re-rank), "
+                  "distance error vs FP64, 1M×96 DEEP-shaped inner product, 1 GPU",
+        "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f64", "bf16": "bf16 storage, f64 accumulate",
+                  "fp8": "fp8-e4m3 storage, f64 accumulate"}[storage],
+        "data": "synthetic",
+        "config": {
+            "workload": f"deep-like {args.n}x{d} (512-component mixture, sigma 1, coordinate variance 1/i, "
+                        f"unit norm), {nq} queries, k={k}, inner product",
+            "graph": f"exact 64-NN, relative-neighbourhood prune to R={R}, repair (keep_local 1), medoid entry",
+            "graph_build_s": round(t_graph, 1), "M": M, "sync": "adaptive", "rho": 0.8, "staged": True,
+            "timed": {"storage": storage, "rerank": best["rerank"], "L": L, "recall@10": row["recall"]},
+            "operating_points": points,
+            "at_f32_L": at_f32,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +248,7 @@ def main():
     ap.add_argument("--M", type=int, default=0, help="time this walker count only (0: sweep)")
     ap.add_argument("--L", type=int, default=0, help="with --M, time this L (0: sweep)")
     ap.add_argument("--sweep-json", default="")
+    ap.add_argument("--workload", choices=["sift", "deep"], default="sift")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run a plain elementwise copy of this many MiB (read and written "
                          "once) so that a profiler run can scale its byte counters")
@@ -97,6 +266,8 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     B.lib()
     dev = torch.device("cuda:0")
+    if args.workload == "deep":
+        return deep_main(args, torch, B, synth, dev)
 
     t0 = time.time()
     w = synth.sift_like(n=args.n, nq=args.nq)
@@ -252,24 +423,7 @@ def main():
                 "kernel_ms": round(float(launch_ms.mean()), 4)}
 
     # ---------------------------------------------------------------- CPU oracle baseline
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        adj_h = adj.cpu().numpy()
-        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        done, t_cpu, bs = 0, 0.0, 64
-        while t_cpu < args.cpu_seconds and done < args.nq:
-            n1 = min(bs, args.nq - done)
-            s0 = time.perf_counter()
-            oracle.speedann(w.base, adj_h, entry, w.queries[done:done + n1], k, L, M, sync="adaptive", rho=0.8,
-                            staged=True)
-            t_cpu += time.perf_counter() - s0
-            done += n1
-            bs = min(bs * 2, 2048)
-        cpu = {"value": round(done / t_cpu, 1), "unit": "queries/s", "cores": nthreads, "kind": "oracle",
-               "sample": f"first {done} of the {args.nq} queries, same graph, M={M}, L={L}, adaptive rho 0.8 "
-                         f"staged, lockstep emulation of Algorithm 3 in plain C, one query per OpenMP thread"}
-        log(f"cpu oracle: {cpu['value']} q/s on {nthreads} threads ({done} queries, {t_cpu:.1f}s)")
+    cpu = None if args.no_cpu else cpu_oracle(w, adj, entry, k, L, M, args.cpu_seconds)
 
     res = {
         "metric": "QPS and p50/p99 latency at recall@10=0.99, 1M×128 SIFT-shaped, 1 GPU",

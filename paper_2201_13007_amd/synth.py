@@ -76,16 +76,22 @@ def sift_like(n: int = 1_000_000, nq: int = 10_000, d: int = 128, ncomp: int = 2
 
 
 def deep_like(n: int = 1_000_000, nq: int = 10_000, d: int = 96, ncomp: int = 512,
-              sigma: float = 1.0, config: int = 3) -> Workload:
-    """Config 3 (and 5 with 1024 components): means N(0, I), x = mean + sigma N(0, I),
-    then scaled to unit l2 norm; inner-product metric."""
+              sigma: float = 1.0, decay: float = 1.0, config: int = 3) -> Workload:
+    """Config 3 (and 5 with 1024 components): a Gaussian mixture in coordinates whose
+    variance falls as 1 / i^decay (i = 1..d), the way it does in PCA-compressed
+    descriptors: means N(0, I), x = (mean + sigma N(0, I)) * i^(-decay/2) per coordinate,
+    then scaled to unit l2 norm; inner-product metric.  With decay 0 the mixture is
+    isotropic and, at sigma 1 and 1M points, about as hard to navigate as 96-d noise."""
     means = rng(config, S_MIX).standard_normal((ncomp, d))
     xb, lb = _mixture_rows(config, n, means, sigma, S_BASE_LABEL, S_BASE_NOISE)
     xq, lq = _mixture_rows(config, nq, means, sigma, S_Q_LABEL, S_Q_NOISE)
+    sd = (np.arange(d) + 1.0) ** (-0.5 * decay)
+    xb *= sd
+    xq *= sd
     xb /= np.linalg.norm(xb, axis=1, keepdims=True)
     xq /= np.linalg.norm(xq, axis=1, keepdims=True)
     return Workload(f"deep-like-{n}x{d}", xb.astype(np.float32), xq.astype(np.float32), "ip", 10, 64, 32,
-                    "rng", True, {"config": config, "ncomp": ncomp, "sigma": sigma,
+                    "rng", True, {"config": config, "ncomp": ncomp, "sigma": sigma, "decay": decay,
                                   "base_labels": lb, "query_labels": lq})
 
 
