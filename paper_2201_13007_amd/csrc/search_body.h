@@ -199,32 +199,22 @@ struct VecSrc {
     int64_t ld;
 };
 
-// value of an e4m3 code (finite variant: bias 7, 3 mantissa bits, subnormals m * 2^-9)
-__device__ __forceinline__ float e4m3_value(uint32_t c)
-{
-    const uint32_t e = (c >> 3) & 15u, m = c & 7u;
-    const float sub = (float)m * 0.001953125f;
-    const float nrm = __uint_as_float(((e + 120u) << 23) | (m << 20));
-    const float v = e == 0u ? sub : nrm;
-    return (c & 0x80u) ? -v : v;
-}
+// Coordinates 4c .. 4c+3 of a row as stored: this raw form is what stays in registers
+// while the loads are in flight, and is decoded where the distance uses it.
+template <int DT> struct Raw4T { using type = uint32_t; };
+template <> struct Raw4T<SA_F32> { using type = float4; };
+template <> struct Raw4T<SA_BF16> { using type = uint2; };
+template <int DT> using Raw4 = typename Raw4T<DT>::type;
 
-// coordinates 4c .. 4c+3 of row id as the float32 values they stand for
 template <int DT>
-__device__ __forceinline__ float4 load4(const VecSrc &V, int32_t id, int c)
+__device__ __forceinline__ Raw4<DT> load_raw4(const VecSrc &V, int32_t id, int c)
 {
-    if constexpr (DT == SA_F32) {
+    if constexpr (DT == SA_F32)
         return *reinterpret_cast<const float4 *>(static_cast<const float *>(V.p) + (int64_t)id * V.ld + 4 * c);
-    } else if constexpr (DT == SA_BF16) {
-        const uint2 w = *(reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(V.p) + (int64_t)id * V.ld) + c);
-        return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u), __uint_as_float(w.y << 16),
-                           __uint_as_float(w.y & 0xFFFF0000u));
-    } else {
-        const uint32_t w = *(reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(V.p) + (int64_t)id * V.ld) + c);
-        const float s = V.scale[id];
-        return make_float4(s * e4m3_value(w & 0xFFu), s * e4m3_value((w >> 8) & 0xFFu),
-                           s * e4m3_value((w >> 16) & 0xFFu), s * e4m3_value(w >> 24));
-    }
+    else if constexpr (DT == SA_BF16)
+        return *(reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(V.p) + (int64_t)id * V.ld) + c);
+    else
+        return *(reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(V.p) + (int64_t)id * V.ld) + c);
 }
 
 // Keys of the vectors ids[0..n) (n <= 64) to out[0..n), 64 / LPV vectors per pass; qs is
@@ -241,7 +231,8 @@ __device__ __forceinline__ void distances(const VecSrc &V, int d, const float *q
     const int lane = __lane_id(), grp = lane / LPV, g = lane % LPV;
     const int nch = d >> 2;
     for (int p0 = 0; p0 < n; p0 += VPW * PB) {
-        float4 x[PB][4];
+        Raw4<DT> x[PB][4];
+        float sc[PB];
         int32_t id[PB];
 #pragma unroll
         for (int pp = 0; pp < PB; ++pp) {
@@ -252,8 +243,9 @@ __device__ __forceinline__ void distances(const VecSrc &V, int d, const float *q
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int c = g + LPV * i;
-                x[pp][i] = load4<DT>(V, row, c < nch ? c : 0);
+                x[pp][i] = load_raw4<DT>(V, row, c < nch ? c : 0);
             }
+            sc[pp] = DT == SA_FP8E4M3 ? V.scale[row] : 1.f;
         }
 #pragma unroll
         for (int pp = 0; pp < PB; ++pp) {
@@ -262,8 +254,33 @@ __device__ __forceinline__ void distances(const VecSrc &V, int d, const float *q
             for (int i = 0; i < 4; ++i) {
                 const bool in = g + LPV * i < nch;
                 const float4 a = reinterpret_cast<const float4 *>(qs)[g + LPV * i];
-                const float bx = in ? x[pp][i].x : 0.f, by = in ? x[pp][i].y : 0.f;
-                const float bz = in ? x[pp][i].z : 0.f, bw = in ? x[pp][i].w : 0.f;
+                // codes outside the row are taken as code 0, which is 0.0 in every storage
+                // type; the selects act on the loaded registers themselves (on a decoded
+                // copy they cost some twenty-five more registers)
+                float bx, by, bz, bw;
+                if constexpr (DT == SA_F32) {
+                    bx = in ? x[pp][i].x : 0.f; by = in ? x[pp][i].y : 0.f;
+                    bz = in ? x[pp][i].z : 0.f; bw = in ? x[pp][i].w : 0.f;
+                } else if constexpr (DT == SA_BF16) {
+                    const uint32_t lo = in ? x[pp][i].x : 0u, hi = in ? x[pp][i].y : 0u;
+                    bx = __uint_as_float(lo << 16); by = __uint_as_float(lo & 0xFFFF0000u);
+                    bz = __uint_as_float(hi << 16); bw = __uint_as_float(hi & 0xFFFF0000u);
+                } else {
+                    // gfx950 converts OCP e4m3 (bias 7, finite; codes 0x7F and 0xFF are NaN)
+                    // in hardware, two codes per instruction, exactly
+                    const uint32_t w = in ? x[pp][i] : 0u;
+                    // e4m3 -> f16 bit pattern (same mantissa, exponent bias 15 instead of 7:
+                    // the value comes out 2^-8 too small, subnormals included)
+                    const uint32_t h0 = ((w & 0x7Fu) << 7) | ((w & 0x80u) << 8);
+                    const uint32_t h1 = ((w >> 8 & 0x7Fu) << 7) | ((w >> 8 & 0x80u) << 8);
+                    const uint32_t h2 = ((w >> 16 & 0x7Fu) << 7) | ((w >> 16 & 0x80u) << 8);
+                    const uint32_t h3 = ((w >> 24 & 0x7Fu) << 7) | ((w >> 24 & 0x80u) << 8);
+                    const float s = sc[pp] * 256.f;
+                    bx = s * (float)__builtin_bit_cast(_Float16, (uint16_t)h0);
+                    by = s * (float)__builtin_bit_cast(_Float16, (uint16_t)h1);
+                    bz = s * (float)__builtin_bit_cast(_Float16, (uint16_t)h2);
+                    bw = s * (float)__builtin_bit_cast(_Float16, (uint16_t)h3);
+                }
                 if constexpr (L2) {
                     const double t0 = (double)a.x - (double)bx, t1 = (double)a.y - (double)by;
                     const double t2 = (double)a.z - (double)bz, t3 = (double)a.w - (double)bw;
