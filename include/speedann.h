@@ -44,9 +44,10 @@ typedef enum { SA_L2 = 0, SA_IP = 1 } sa_metric;
  *   SA_BF16     bfloat16: the upper half of the float32 pattern rounded to nearest even;
  *               no scale (a value is its code)
  *   SA_FP8E4M3  8-bit e4m3, finite variant (bias 7, 3 mantissa bits, subnormals m * 2^-9,
- *               largest 448, no infinities; codes 0x7F and 0xFF are NaN and sa_quantize
- *               never writes them) with a float32 scale per vector: a coordinate stands
- *               for scale * value(code), computed in float32.
+ *               largest 448, no infinities; codes 0x7F and 0xFF are NaN in the format,
+ *               sa_quantize never writes them and an index must not hold them) with a
+ *               float32 scale per vector: a coordinate stands for scale * value(code),
+ *               computed in float32.
  * Distances are computed on these values exactly as on float32 vectors. */
 typedef enum { SA_F32 = 0, SA_BF16 = 1, SA_FP8E4M3 = 2 } sa_dtype;
 

@@ -266,11 +266,13 @@ __device__ __forceinline__ void distances(const VecSrc &V, int d, const float *q
                     bx = __uint_as_float(lo << 16); by = __uint_as_float(lo & 0xFFFF0000u);
                     bz = __uint_as_float(hi << 16); bw = __uint_as_float(hi & 0xFFFF0000u);
                 } else {
-                    // gfx950 converts OCP e4m3 (bias 7, finite; codes 0x7F and 0xFF are NaN)
-                    // in hardware, two codes per instruction, exactly
+                    // e4m3 -> f16 bit pattern: same mantissa bits, exponent bias 15 instead
+                    // of 7, so every value, subnormals included, comes out 2^-8 too small;
+                    // 2^8 joins the scale, and s * 2^8 * v rounds once like s * value.  (The
+                    // hardware fp8 conversion gives the same values but its vector results
+                    // cost the caller about twenty registers.)  Codes 0x7F / 0xFF, NaN in
+                    // e4m3, are never written and decode as 480 / -480 here.
                     const uint32_t w = in ? x[pp][i] : 0u;
-                    // e4m3 -> f16 bit pattern (same mantissa, exponent bias 15 instead of 7:
-                    // the value comes out 2^-8 too small, subnormals included)
                     const uint32_t h0 = ((w & 0x7Fu) << 7) | ((w & 0x80u) << 8);
                     const uint32_t h1 = ((w >> 8 & 0x7Fu) << 7) | ((w >> 8 & 0x80u) << 8);
                     const uint32_t h2 = ((w >> 16 & 0x7Fu) << 7) | ((w >> 16 & 0x80u) << 8);
