@@ -237,6 +237,60 @@ int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64
               int32_t M, const sa_search_params *params, int32_t *ids_dev, float *dists_dev,
               sa_query_stats *stats_dev, void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* ------------------------------------------------------------------ batches
+ *
+ * A batch is a fixed set of nq queries, each with its own L, k and M, searched together:
+ * the inter-query parallelism of Sec. 1 on top of the intra-query parallelism of
+ * Algorithm 3.  The result of every query is exactly
+ * the one sa_search gives for it alone with its own (L, k, M) and the batch's shared
+ * params, whatever the batch holds and however it is tuned.
+ *
+ * The plan groups the queries into classes of equal M and equal register-queue size
+ * (ceil(L / 64) rounded up to 1, 2, 4, 6, 8 or 16), one kernel launch each, longest L
+ * first within a class; classes go to up to four internal streams.  sa_batch_run only
+ * enqueues kernel launches and event records and waits, so it can be captured in a HIP
+ * graph from hip_stream (the classes become parallel branches) and replayed.  The
+ * workspace holds the uploaded per-query arrays and one visited-set region per query
+ * (as sa_search sizes them for the class's largest L); the search regions are zero
+ * between runs.  Re-rank (params->rerank != 0) is not supported in a batch. */
+typedef struct sa_batch sa_batch;
+
+/* L, k, M: host arrays of nq entries, copied (1 <= k <= L <= 1024, 1 <= M <= 16).
+ * params: NULL for defaults; shared by every query. */
+int sa_batch_create(const sa_index *index, int64_t nq, const int32_t *L, const int32_t *k, const int32_t *M,
+                    const sa_search_params *params, sa_batch **out);
+void sa_batch_destroy(sa_batch *batch);
+size_t sa_batch_workspace_bytes(const sa_batch *batch);
+
+/* Writes the batch's per-query arrays into workspace (sa_batch_workspace_bytes bytes,
+ * 256-byte aligned, zero-filled before its first use) and waits for the copy.  Once per
+ * workspace, before the first run or tune on it; not for capture. */
+int sa_batch_upload(const sa_batch *batch, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Searches the batch: queries_dev nq x d float32 (stride ldq), ids_dev / dists_dev rows
+ * of stride ldo >= the largest k, of which row q gets its first k[q] entries (the rest
+ * is not written), stats_dev NULL or nq sa_query_stats.  Allocates nothing; enqueued on
+ * hip_stream (forking onto the batch's streams and joining back); runs that share a
+ * workspace must not overlap. */
+int sa_batch_run(const sa_batch *batch, const float *queries_dev, int64_t ldq, int32_t *ids_dev, float *dists_dev,
+                 int64_t ldo, sa_query_stats *stats_dev, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Autotuner: times sa_batch_run (best of reps after one warm run) for 1, 2 and 4
+ * streams and, when a class has two or more walkers and params left lds_hash_slots at
+ * 0, with and without LDS visited tables for those classes; keeps the fastest.  Results
+ * do not depend on the choice.  Synchronous; overwrites ids_dev and dists_dev. */
+int sa_batch_tune(sa_batch *batch, const float *queries_dev, int64_t ldq, int32_t *ids_dev, float *dists_dev,
+                  int64_t ldo, void *workspace, size_t ws_bytes, int32_t reps, void *hip_stream);
+
+/* Sets the configuration by hand: streams 1, 2 or 4; lds_hash_slots for the classes with
+ * two or more walkers (as in sa_search_params). */
+int sa_batch_set_config(sa_batch *batch, int32_t streams, int32_t lds_hash_slots);
+
+/* JSON description of the plan (classes, their sizes, configuration, last tuning) into
+ * buf (NUL-terminated, truncated to len); returns the length it needs including the NUL,
+ * or a negative status. */
+int64_t sa_batch_describe(const sa_batch *batch, char *buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,9 @@ SYNC = {"bsp": 0, "static": 1, "adaptive": 2}
 QFLAG_MAX_STEPS, QFLAG_CAPACITY, QFLAG_SPILLED = 1, 2, 4
 
 EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_quantize", "sa_index_create_q", "sa_medoid", "sa_prune", "sa_reverse_edges",
-           "sa_repair", "sa_build_graph", "sa_index_create", "sa_index_destroy", "sa_search_workspace_bytes", "sa_search"]
+           "sa_repair", "sa_build_graph", "sa_index_create", "sa_index_destroy", "sa_search_workspace_bytes", "sa_search",
+           "sa_batch_create", "sa_batch_destroy", "sa_batch_workspace_bytes", "sa_batch_upload", "sa_batch_run",
+           "sa_batch_tune", "sa_batch_set_config", "sa_batch_describe"]
 
 
 class SearchParams(C.Structure):
@@ -68,8 +70,20 @@ def lib():
         L.sa_search_workspace_bytes.argtypes = [vp, i64, i32, i32, i32, C.POINTER(SearchParams)]
         L.sa_search_workspace_bytes.restype = sz
         L.sa_search.argtypes = [vp, vp, i64, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp, sz, vp]
+        L.sa_batch_create.argtypes = [vp, i64, vp, vp, vp, C.POINTER(SearchParams), C.POINTER(vp)]
+        L.sa_batch_destroy.argtypes = [vp]
+        L.sa_batch_destroy.restype = None
+        L.sa_batch_workspace_bytes.argtypes = [vp]
+        L.sa_batch_workspace_bytes.restype = sz
+        L.sa_batch_upload.argtypes = [vp, vp, sz, vp]
+        L.sa_batch_run.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, sz, vp]
+        L.sa_batch_tune.argtypes = [vp, vp, i64, vp, vp, i64, vp, sz, i32, vp]
+        L.sa_batch_set_config.argtypes = [vp, i32, i32]
+        L.sa_batch_describe.argtypes = [vp, C.c_char_p, sz]
+        L.sa_batch_describe.restype = i64
         for name in ("sa_knn", "sa_knn_ex", "sa_quantize", "sa_index_create_q", "sa_medoid", "sa_prune", "sa_reverse_edges", "sa_repair", "sa_build_graph", "sa_index_create",
-                     "sa_search"):
+                     "sa_search", "sa_batch_create", "sa_batch_upload", "sa_batch_run", "sa_batch_tune",
+                     "sa_batch_set_config"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -306,3 +320,77 @@ class Index:
                                ids.data_ptr(), dists.data_ptr(), st.data_ptr() if st is not None else None,
                                ws.data_ptr(), ws.numel(), _stream(stream)), "sa_search")
         return SearchResult(ids, dists, st)
+
+
+class Batch:
+    """A batch of queries with per-query (L, k, M) over an Index (sa_batch_*).
+
+    run() enqueues only kernel launches and events on the current (or given) stream, so
+    it can be captured in a torch.cuda.CUDAGraph and replayed."""
+
+    def __init__(self, index: "Index", L, k, M, params: SearchParams | None = None, **kw):
+        import numpy as np
+        self.index = index
+        Ls = np.ascontiguousarray(np.asarray(L, dtype=np.int32))
+        ks = np.ascontiguousarray(np.asarray(k, dtype=np.int32))
+        Ms = np.ascontiguousarray(np.asarray(M, dtype=np.int32))
+        if not (Ls.shape == ks.shape == Ms.shape) or Ls.ndim != 1:
+            raise SpeedAnnError("L, k and M must be 1-d arrays of one length")
+        self.nq = int(Ls.shape[0])
+        self.kmax = int(ks.max()) if self.nq else 1
+        self.k = ks
+        if params is None:
+            params = make_params(**kw)
+        self.params = params
+        h = C.c_void_p()
+        _check(lib().sa_batch_create(index._h, self.nq, Ls.ctypes.data, ks.ctypes.data, Ms.ctypes.data,
+                                     C.byref(params), C.byref(h)), "sa_batch_create")
+        self._h = h
+        self._lib = lib()
+        nbytes = int(lib().sa_batch_workspace_bytes(h))
+        self.ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=index.vec.device)
+        _check(lib().sa_batch_upload(h, self.ws.data_ptr(), self.ws.numel(), _stream(None)), "sa_batch_upload")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        L = getattr(self, "_lib", None)
+        if h is not None and h.value and L is not None:
+            L.sa_batch_destroy(h)
+            self._h = None
+
+    def outputs(self, stats=False):
+        dev = self.index.vec.device
+        ids = torch.full((self.nq, self.kmax), -1, dtype=torch.int32, device=dev)
+        dists = torch.full((self.nq, self.kmax), float("inf"), dtype=torch.float32, device=dev)
+        st = torch.empty((self.nq, STATS_BYTES // 4), dtype=torch.int32, device=dev) if stats else None
+        return ids, dists, st
+
+    def run(self, queries: torch.Tensor, out=None, stats=False, stream=None) -> SearchResult:
+        queries = pad_dim(_mat(queries, "queries"))
+        if queries.shape[0] != self.nq:
+            raise SpeedAnnError("the batch was planned for a different number of queries")
+        ids, dists, st = out if out is not None else self.outputs(stats)
+        _check(lib().sa_batch_run(self._h, queries.data_ptr(), queries.stride(0), ids.data_ptr(), dists.data_ptr(),
+                                  ids.stride(0), st.data_ptr() if st is not None else None, self.ws.data_ptr(),
+                                  self.ws.numel(), _stream(stream)), "sa_batch_run")
+        return SearchResult(ids, dists, st)
+
+    def tune(self, queries: torch.Tensor, reps: int = 3, stream=None) -> dict:
+        queries = pad_dim(_mat(queries, "queries"))
+        ids, dists, _ = self.outputs()
+        _check(lib().sa_batch_tune(self._h, queries.data_ptr(), queries.stride(0), ids.data_ptr(), dists.data_ptr(),
+                                   ids.stride(0), self.ws.data_ptr(), self.ws.numel(), int(reps), _stream(stream)),
+               "sa_batch_tune")
+        return self.describe()["tuning"]
+
+    def set_config(self, streams: int, lds_hash_slots: int = 0):
+        _check(lib().sa_batch_set_config(self._h, int(streams), int(lds_hash_slots)), "sa_batch_set_config")
+
+    def describe(self) -> dict:
+        import json
+        n = int(lib().sa_batch_describe(self._h, None, 0))
+        if n < 0:
+            _check(n, "sa_batch_describe")
+        buf = C.create_string_buffer(n)
+        lib().sa_batch_describe(self._h, buf, n)
+        return json.loads(buf.value.decode())

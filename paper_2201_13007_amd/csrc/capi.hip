@@ -36,7 +36,7 @@ int repair_device(const float *base, int64_t n, int d, int64_t ld, int metric, i
 int reverse_edges_device(const float *base, int64_t n, int d, int64_t ld, int metric, int32_t *adj_dev, int R,
                          int64_t *added_out, hipStream_t s);
 
-static int check_device()
+int check_device()
 {
     static int cached = 0;   // 0 unknown, 1 ok, negative error
     if (cached == 1) return SA_OK;
@@ -53,7 +53,7 @@ static int check_device()
     return SA_OK;
 }
 
-static int check_matrix(const void *p, int64_t rows, int32_t d, int64_t ld, const char *name)
+int check_matrix(const void *p, int64_t rows, int32_t d, int64_t ld, const char *name)
 {
     if (rows < 0) return set_error(SA_EINVAL, "%s: negative row count", name);
     if (rows > 0 && p == nullptr) return set_error(SA_EINVAL, "%s is NULL", name);
@@ -64,22 +64,23 @@ static int check_matrix(const void *p, int64_t rows, int32_t d, int64_t ld, cons
     return SA_OK;
 }
 
+int check_search(const sa_index *ix, int64_t nq, int32_t k, int32_t L, int32_t M, const sa_search_params &p)
+{
+    if (!ix) return set_error(SA_EINVAL, "index is NULL");
+    if (nq < 0 || nq > 0x7FFFFFFF) return set_error(SA_EINVAL, "nq=%lld out of range", (long long)nq);
+    if (k < 1 || L < k || L > 1024) return set_error(SA_EINVAL, "need 1 <= k <= L <= 1024 (k=%d, L=%d)", k, L);
+    if (M < 1 || M > 16) return set_error(SA_EINVAL, "M=%d must be in [1, 16]", M);
+    if (p.sync < SA_SYNC_BSP || p.sync > SA_SYNC_ADAPTIVE) return set_error(SA_EINVAL, "unknown sync %d", p.sync);
+    if (!(p.rho >= 0.0f) || !std::isfinite(p.rho)) return set_error(SA_EINVAL, "rho must be finite and >= 0");
+    if (p.max_substeps < 0) return set_error(SA_EINVAL, "max_substeps must be >= 0");
+    if (p.rerank < -1) return set_error(SA_EINVAL, "rerank=%d must be -1, 0 or positive", p.rerank);
+    if (p.rerank != 0 && !ix->vec32) return set_error(SA_EINVAL, "re-rank needs the index's float32 vectors");
+    return SA_OK;
+}
+
 }  // namespace sa
 
 using namespace sa;
-
-struct sa_index {
-    const void *codes;    // stored vectors, rows of ldc elements of dtype
-    const float *scale;   // fp8 scales
-    int64_t ldc;
-    int32_t dtype;
-    const float *vec32;   // float32 vectors for the re-rank (may be null)
-    int64_t ld32;
-    int64_t n;
-    int32_t d, metric;
-    const int32_t *adj;
-    int32_t R, entry;
-};
 
 extern "C" {
 
@@ -263,19 +264,6 @@ int sa_quantize(const float *x_dev, int64_t n, int32_t d, int64_t ld, int32_t dt
 
 void sa_index_destroy(sa_index *index) { delete index; }
 
-static int check_search(const sa_index *ix, int64_t nq, int32_t k, int32_t L, int32_t M, const sa_search_params &p)
-{
-    if (!ix) return set_error(SA_EINVAL, "index is NULL");
-    if (nq < 0 || nq > 0x7FFFFFFF) return set_error(SA_EINVAL, "nq=%lld out of range", (long long)nq);
-    if (k < 1 || L < k || L > 1024) return set_error(SA_EINVAL, "need 1 <= k <= L <= 1024 (k=%d, L=%d)", k, L);
-    if (M < 1 || M > 16) return set_error(SA_EINVAL, "M=%d must be in [1, 16]", M);
-    if (p.sync < SA_SYNC_BSP || p.sync > SA_SYNC_ADAPTIVE) return set_error(SA_EINVAL, "unknown sync %d", p.sync);
-    if (!(p.rho >= 0.0f) || !std::isfinite(p.rho)) return set_error(SA_EINVAL, "rho must be finite and >= 0");
-    if (p.max_substeps < 0) return set_error(SA_EINVAL, "max_substeps must be >= 0");
-    if (p.rerank < -1) return set_error(SA_EINVAL, "rerank=%d must be -1, 0 or positive", p.rerank);
-    if (p.rerank != 0 && !ix->vec32) return set_error(SA_EINVAL, "re-rank needs the index's float32 vectors");
-    return SA_OK;
-}
 
 size_t sa_search_workspace_bytes(const sa_index *index, int64_t nq, int32_t k, int32_t L, int32_t M,
                                  const sa_search_params *params)

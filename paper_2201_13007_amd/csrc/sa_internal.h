@@ -83,6 +83,10 @@ struct SearchLaunch {
     sa_query_stats *stats;
     void *workspace;
     size_t ws_bytes;
+    // batches (device arrays, or null): per-query L and k, and the query each workgroup
+    // runs; L above is then the largest L and nq the number of workgroups
+    const int32_t *qL = nullptr, *qk = nullptr, *order = nullptr;
+    int64_t ldo = 0;       // row stride of ids and dists (0: k)
 };
 
 int launch_quantize(const float *x, int64_t n, int32_t d, int64_t ld, int32_t dtype, void *codes, int64_t ldc,
@@ -90,5 +94,28 @@ int launch_quantize(const float *x, int64_t n, int32_t d, int64_t ld, int32_t dt
 
 size_t search_workspace_bytes(int64_t nq, int32_t L, int32_t M, const sa_search_params &p, int32_t R);
 int launch_search(const SearchLaunch &a, hipStream_t stream);
+// LDS bytes one workgroup of the general kernel needs, and the visited-table sizes
+// (log2; lds 0 = none) a search with these parameters takes
+uint32_t search_lds_bytes(int32_t L, int32_t M, int32_t llog2, int32_t d);
+void search_table_log2(const sa_search_params &p, int32_t L, int32_t M, int32_t R, int32_t *llog2, int32_t *glog2);
+
+// ---------------------------------------------------------------- C ABI helpers (host)
+
+int check_device();
+int check_matrix(const void *p, int64_t rows, int32_t d, int64_t ld, const char *name);
+int check_search(const sa_index *ix, int64_t nq, int32_t k, int32_t L, int32_t M, const sa_search_params &p);
 
 }  // namespace sa
+
+struct sa_index {
+    const void *codes;    // stored vectors, rows of ldc elements of dtype
+    const float *scale;   // fp8 scales
+    int64_t ldc;
+    int32_t dtype;
+    const float *vec32;   // float32 vectors for the re-rank (may be null)
+    int64_t ld32;
+    int64_t n;
+    int32_t d, metric;
+    const int32_t *adj;
+    int32_t R, entry;
+};

@@ -87,6 +87,17 @@ size_t bytes_per_slot(int M, int llog2) { return compact_table(M, llog2) ? 8 : 1
 
 }  // namespace
 
+uint32_t search_lds_bytes(int32_t L, int32_t M, int32_t llog2, int32_t d)
+{
+    return make_layout(L, M, llog2, search_detail::lanes_per_vector(d)).total;
+}
+
+void search_table_log2(const sa_search_params &p, int32_t L, int32_t M, int32_t R, int32_t *llog2, int32_t *glog2)
+{
+    int ms;
+    resolve_params(p, L, M, R, *llog2, *glog2, ms);
+}
+
 size_t search_workspace_bytes(int64_t nq, int32_t L, int32_t M, const sa_search_params &p, int32_t R)
 {
     int llog2, glog2, max_sub;
@@ -118,6 +129,8 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     KArgs A;
     A.codes = a.codes; A.scale = a.scale; A.ldc = a.ldc; A.vec32 = a.vec32; A.ld32 = a.ld32; A.rerank = a.p.rerank;
     A.adj = a.adj; A.queries = a.queries; A.ldq = a.ldq;
+    A.qL = a.qL; A.qk = a.qk; A.order = a.order; A.ldo = a.ldo > 0 ? a.ldo : a.k;
+    if (a.order && a.p.rerank != 0) return set_error(SA_EUNSUPPORTED, "a batch cannot re-rank");
     A.ids = a.ids; A.dists = a.dists; A.stats = a.stats;
     A.ghash = reinterpret_cast<unsigned long long *>(a.workspace);
     A.n = a.n;

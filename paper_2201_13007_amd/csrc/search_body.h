@@ -78,6 +78,10 @@ struct KArgs {
     double rho;
     int32_t glog2, llog2;        // llog2 == 0: no LDS table
     uint32_t o_skey, o_srank, o_schk, o_pub, o_newkey, o_claim, o_ctrl, o_hash, o_q;
+    // batches: per-query L and k (null: L and k above) and the query each workgroup
+    // runs (null: workgroup b runs query b)
+    const int32_t *qL, *qk, *order;
+    int64_t ldo;                 // row stride of ids and dists
 };
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
@@ -470,8 +474,11 @@ __device__ __forceinline__ void search_body(const KArgs &A)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6, nthr = blockDim.x;
-    const int64_t qi = blockIdx.x;
-    const int L = A.L, M = A.M, R = A.R;
+    // workgroup b runs query order[b] (or b) in workspace region b
+    const int64_t job = blockIdx.x;
+    const int64_t qi = A.order ? A.order[job] : job;
+    const int L = A.qL ? A.qL[qi] : A.L, M = A.M, R = A.R;
+    const int kq = A.qk ? A.qk[qi] : A.k;
 
     uint64_t *const skey_base = reinterpret_cast<uint64_t *>(smem + A.o_skey);
     int32_t *const srank = reinterpret_cast<int32_t *>(smem + A.o_srank);
@@ -481,7 +488,7 @@ __device__ __forceinline__ void search_body(const KArgs &A)
     int32_t *const claim = reinterpret_cast<int32_t *>(smem + A.o_claim) + w * 64;
     Ctrl *const C = reinterpret_cast<Ctrl *>(smem + A.o_ctrl);
     unsigned long long *const lh = reinterpret_cast<unsigned long long *>(smem + A.o_hash);
-    unsigned long long *const gh = A.ghash ? A.ghash + ((size_t)qi << (A.glog2 + 1)) : nullptr;
+    unsigned long long *const gh = A.ghash ? A.ghash + ((size_t)job << (A.glog2 + 1)) : nullptr;
     uint32_t *const gslots = gh ? reinterpret_cast<uint32_t *>(gh + (1ull << A.glog2)) : nullptr;
 
     const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
@@ -957,22 +964,22 @@ __device__ __forceinline__ void search_body(const KArgs &A)
 #pragma unroll
                 for (int i = 0; i < NI; ++i) {
                     const int p = i * 64 + lane;
-                    if (p < A.k) {
+                    if (p < kq) {
                         const bool ok = p < slen;
-                        A.ids[qi * A.k + p] = ok ? key_id(ls.k[i]) : -1;
-                        A.dists[qi * A.k + p] = ok ? key_dist(ls.k[i]) : __builtin_inff();
+                        A.ids[qi * A.ldo + p] = ok ? key_id(ls.k[i]) : -1;
+                        A.dists[qi * A.ldo + p] = ok ? key_dist(ls.k[i]) : __builtin_inff();
                     }
                 }
             }
         } else {
             const uint64_t *S = skey_base + sb * L;
-            for (int i = tid; i < A.k; i += nthr) {
+            for (int i = tid; i < kq; i += nthr) {
                 if (i < slen) {
-                    A.ids[qi * A.k + i] = key_id(S[i]);
-                    A.dists[qi * A.k + i] = key_dist(S[i]);
+                    A.ids[qi * A.ldo + i] = key_id(S[i]);
+                    A.dists[qi * A.ldo + i] = key_dist(S[i]);
                 } else {
-                    A.ids[qi * A.k + i] = -1;
-                    A.dists[qi * A.k + i] = __builtin_inff();
+                    A.ids[qi * A.ldo + i] = -1;
+                    A.dists[qi * A.ldo + i] = __builtin_inff();
                 }
             }
         }

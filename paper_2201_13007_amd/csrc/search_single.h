@@ -169,7 +169,7 @@ __device__ __forceinline__ uint32_t claim(uint32_t *T, int log2cap, uint32_t u, 
 }
 
 template <int LPV, int NI, bool L2, int DT>
-__global__ void __launch_bounds__(64) search_single(KArgs A)
+__device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_t *tbl)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     uint64_t *const nkey = reinterpret_cast<uint64_t *>(smem);    // [64] keys of new vertices
@@ -177,10 +177,10 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
     float *const qs = reinterpret_cast<float *>(sid + 64);          // [16 LPV] the query
 
     const int lane = __lane_id();
-    const int64_t qi = blockIdx.x;
+    const int R = A.R, g2 = A.glog2;
+    const int L = A.qL ? A.qL[qi] : A.L;
+    const int kq = A.qk ? A.qk[qi] : A.k;
     const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
-    const int L = A.L, R = A.R, g2 = A.glog2;
-    uint32_t *const tbl = reinterpret_cast<uint32_t *>(A.ghash) + ((size_t)qi << (g2 + 1));
     uint32_t *const slots = tbl + (1u << g2);
     const int cap = (3 << g2) / 4;
     const VecSrc V{A.codes, A.scale, A.ldc};
@@ -292,10 +292,10 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
             const int p = 64 * i + lane;
-            if (p < A.k) {
+            if (p < kq) {
                 const bool ok = p < Q.len;
-                A.ids[qi * A.k + p] = ok ? key_id(Q.k[i]) : -1;
-                A.dists[qi * A.k + p] = ok ? key_dist(Q.k[i]) : __builtin_inff();
+                A.ids[qi * A.ldo + p] = ok ? key_id(Q.k[i]) : -1;
+                A.dists[qi * A.ldo + p] = ok ? key_dist(Q.k[i]) : __builtin_inff();
             }
         }
     }
@@ -316,6 +316,19 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
         st.t_end = __builtin_amdgcn_s_memrealtime();
         A.stats[qi] = st;
     }
+}
+
+// Workgroup b runs job b: query order[b] (or b), in workspace region b.  The hardware
+// dispatcher hands out workgroups in index order as slots free up, so a batch ordered
+// longest first is scheduled longest first.  (A persistent loop over jobs in one
+// workgroup was measured: any loop around the search costs 17-36 more VGPRs, about a
+// third of the occupancy this latency-bound search lives on.)
+template <int LPV, int NI, bool L2, int DT>
+__global__ void __launch_bounds__(64) search_single(KArgs A)
+{
+    const int32_t job = blockIdx.x;
+    uint32_t *const tbl = reinterpret_cast<uint32_t *>(A.ghash) + ((size_t)job << (A.glog2 + 1));
+    single_query<LPV, NI, L2, DT>(A, A.order ? A.order[job] : job, tbl);
 }
 
 template <int LPV, int NI, int DT>

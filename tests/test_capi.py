@@ -67,6 +67,23 @@ def test_validation_errors_without_device(B):
     p.rho = float("nan")
     assert L.sa_search(ix, fake, 4, 32, 10, 64, 4, C.byref(p), fake, fake, None, fake, 1 << 30, None) == -1
     assert "rho" in _err(B)
+    # batches: every query is checked before anything is allocated; no re-rank
+    import numpy as np
+    bL = np.array([64, 10, 64], np.int32)
+    bk = np.array([10, 20, 10], np.int32)
+    bM = np.array([1, 1, 4], np.int32)
+    bh = C.c_void_p(0)
+    L.sa_default_params(C.byref(p))
+    assert L.sa_batch_create(ix, 3, bL.ctypes.data, bk.ctypes.data, bM.ctypes.data, C.byref(p), C.byref(bh)) == -1
+    assert "query 1" in _err(B) and not bh.value
+    p.rerank = -1
+    bk[1] = 5
+    assert L.sa_batch_create(ix, 3, bL.ctypes.data, bk.ctypes.data, bM.ctypes.data, C.byref(p), C.byref(bh)) != 0
+    assert "re-rank" in _err(B)
+    p.rerank = 0
+    assert L.sa_batch_create(ix, 3, None, bk.ctypes.data, bM.ctypes.data, C.byref(p), C.byref(bh)) == -1
+    assert L.sa_batch_workspace_bytes(None) == 0
+    assert L.sa_batch_describe(None, None, 0) < 0
     L.sa_index_destroy(ix)
     # exact kNN argument checks
     assert L.sa_knn(fake, 10, 32, 32, fake, 3, 32, 0, 0, 0, fake, fake, None) == -1

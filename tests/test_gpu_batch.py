@@ -1,0 +1,151 @@
+"""GPU parity for batches with per-query (L, k, M) (sa_batch_*).
+
+Every query of a batch must give exactly what the oracle gives for it alone with its own
+(L, k, M): ids and counters exact, distances within 1e-5 relative.  The batch must equal
+sa_search per query under every configuration the autotuner can pick, and a HIP graph
+captured from a run must replay to the same result.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_13007_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2201_13007_amd import binding
+    binding.lib()
+    return binding
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def gist():
+    # GIST-shaped mix at small size: L log-uniform in [32, 1024], k in {1, 10, 100}, M in
+    # {1, 4, 8}, L raised to k where it falls below
+    w = synth.gist_like(n=4000, nq=96)
+    adj, entry, _ = oracle.build_graph(w.base, 32, 24, "rng", do_repair=True)
+    L = np.maximum(w.info["L"], w.info["k"]).astype(np.int32)
+    return w, adj, entry, L, w.info["k"].astype(np.int32), w.info["M"].astype(np.int32)
+
+
+def test_batch_matches_oracle_per_query(B, gist):
+    w, adj, entry, L, k, M = gist
+    print(f"case: batch gist-4000x960 nq={len(L)} mixed L/k/M", flush=True)
+    ix = B.Index(dev(w.base), dev(adj), entry)
+    bt = B.Batch(ix, L, k, M, rho=0.8)
+    r = bt.run(dev(w.queries), stats=True)
+    gids, gd, gst = host(r.ids), host(r.dists), host(r.stats)
+    for q in range(len(L)):
+        eids, ed, est = oracle.speedann(w.base, adj, entry, w.queries[q:q + 1], int(k[q]), int(L[q]), int(M[q]),
+                                        rho=0.8)
+        kq = int(k[q])
+        assert (gids[q, :kq] == eids[0]).all(), f"query {q} (L={L[q]} k={kq} M={M[q]}): ids differ"
+        np.testing.assert_allclose(gd[q, :kq], ed[0], rtol=1e-5, err_msg=f"query {q}")
+        assert (gids[q, kq:] == -1).all(), "entries past k must stay unwritten"
+        for j, name in enumerate(["global_steps", "substeps", "expansions", "dist_comps", "merges"]):
+            assert gst[q, j] == est[name][0], f"query {q} {name}"
+
+
+def test_batch_equals_search_under_every_config(B, gist):
+    w, adj, entry, L, k, M = gist
+    ix = B.Index(dev(w.base), dev(adj), entry)
+    q = dev(w.queries)
+    want_ids = np.full((len(L), int(k.max())), -1, np.int32)
+    want_d = np.full((len(L), int(k.max())), np.inf, np.float32)
+    for i in range(len(L)):
+        r = ix.search(q[i:i + 1], int(k[i]), int(L[i]), int(M[i]), rho=0.8)
+        want_ids[i, :k[i]] = host(r.ids)[0]
+        want_d[i, :k[i]] = host(r.dists)[0]
+    bt = B.Batch(ix, L, k, M, rho=0.8)
+    for streams in (1, 2, 4):
+        for lds in (0, -1, 4096):
+            print(f"case: batch config streams={streams} lds_hash_slots={lds}", flush=True)
+            bt.set_config(streams, lds)
+            r = bt.run(q)
+            np.testing.assert_array_equal(host(r.ids), want_ids)
+            np.testing.assert_array_equal(host(r.dists), want_d)
+    print("case: batch tune", flush=True)
+    t = bt.tune(q, reps=1)
+    assert len(t["candidates"]) >= 3 and t["chosen"]["streams"] in (1, 2, 4)
+    r = bt.run(q)
+    np.testing.assert_array_equal(host(r.ids), want_ids)
+    d = bt.describe()
+    assert sum(c["queries"] for c in d["classes"]) == len(L)
+    assert {c["M"] for c in d["classes"]} == set(M.tolist())
+
+
+def test_batch_graph_replay(B, gist):
+    w, adj, entry, L, k, M = gist
+    ix = B.Index(dev(w.base), dev(adj), entry)
+    q = dev(w.queries)
+    bt = B.Batch(ix, L, k, M, rho=0.8)
+    bt.set_config(4, 0)
+    eager = bt.run(q)
+    e_ids, e_d = host(eager.ids), host(eager.dists)
+    out = bt.outputs()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bt.run(q, out=out)          # warm on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    print("case: batch captured in a graph, 3 replays", flush=True)
+    with torch.cuda.graph(g):
+        bt.run(q, out=out)
+    written = np.arange(e_ids.shape[1])[None, :] < k[:, None]   # row q gets its first k[q] entries
+    for rep in range(3):
+        out[0].fill_(-7)
+        out[1].fill_(-7.0)
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(out[0])[written], e_ids[written], err_msg=f"replay {rep}")
+        np.testing.assert_array_equal(host(out[1])[written], e_d[written], err_msg=f"replay {rep}")
+        assert (host(out[0])[~written] == -7).all()
+        # eager work between replays
+        again = bt.run(q)
+        np.testing.assert_array_equal(host(again.ids), e_ids)
+
+
+def test_batch_one_class_and_sift(B):
+    w = synth.sift_like(n=5000, nq=40)
+    adj, entry, _ = oracle.build_graph(w.base, 32, 24, "rng", do_repair=True)
+    L = np.full(40, 96, np.int32)
+    k = np.full(40, 10, np.int32)
+    M = np.full(40, 2, np.int32)
+    print("case: batch sift-5000 one class M=2 L=96", flush=True)
+    ix = B.Index(dev(w.base), dev(adj), entry)
+    r = B.Batch(ix, L, k, M).run(dev(w.queries), stats=True)
+    eids, ed, est = oracle.speedann(w.base, adj, entry, w.queries, 10, 96, 2)
+    np.testing.assert_array_equal(host(r.ids), eids)
+    np.testing.assert_array_equal(host(r.dists), ed)   # integer data: exact
+    np.testing.assert_array_equal(host(r.stats)[:, 3], est["dist_comps"])
+
+
+def test_batch_errors(B, gist):
+    w, adj, entry, L, k, M = gist
+    ix = B.Index(dev(w.base), dev(adj), entry)
+    with pytest.raises(B.SpeedAnnError, match="re-rank"):
+        B.Batch(ix, L, k, M, rerank=-1)
+    bad = k.copy()
+    bad[5] = L[5] + 1
+    with pytest.raises(B.SpeedAnnError, match="query 5"):
+        B.Batch(ix, L, bad, M)
+    bt = B.Batch(ix, L, k, M)
+    with pytest.raises(B.SpeedAnnError, match="different number"):
+        bt.run(dev(w.queries[:10]))
