@@ -15,6 +15,12 @@ own operating point (smallest swept L reaching recall@10 0.99) and compared with
 float32 path at equal L: recall, QPS and the error of the returned distances against
 FP64.
 
+With --workload gist: the GIST-shaped 1M x 960 batch (128-component mixture, sigma 0.1),
+20,000 queries each with its own L (log-uniform in [32, 1024], raised to k), k in
+{1, 10, 100} and M in {1, 4, 8}, searched as one batch: planned into classes, tuned,
+captured in a HIP graph and replayed.  A step is one replay.  The plain path for the
+same results, one search call per distinct (L, k, M), is timed beside it.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -235,20 +241,165 @@ def deep_main(args, torch, B, synth, dev):
     print(json.dumps(res), flush=True)
 
 
+def build_graph_logged(torch, B, base, knn_k, R, prune_mode, chunk=100_000):
+    """The steps of sa_build_graph (medoid entry, exact knn_k-NN candidates, pruning,
+    reverse edges, repair), with the candidate search cut into row chunks so that each
+    finished chunk is logged.  A chunk's rows search the whole base with k = knn_k + 1
+    and drop their own id, which leaves the same knn_k candidates as excluding it."""
+    n = base.shape[0]
+    entry = B.medoid(base)
+    cand = torch.empty((n, knn_k), dtype=torch.int32, device=base.device)
+    t0 = time.time()
+    for s0 in range(0, n, chunk):
+        e0 = min(n, s0 + chunk)
+        ids, _ = B.knn(base, base[s0:e0], knn_k + 1)
+        own = torch.arange(s0, e0, device=base.device, dtype=torch.int32)[:, None]
+        keep = ids != own
+        # rows where the own id is not among the knn_k + 1 keep their first knn_k
+        first = torch.cumsum(keep.to(torch.int32), 1) <= knn_k
+        cand[s0:e0] = ids[keep & first].view(e0 - s0, knn_k)
+        torch.cuda.synchronize()
+        log(f"candidates: rows {e0:,} of {n:,} in {time.time() - t0:.1f}s")
+    adj = B.prune(base, cand, R, prune_mode)
+    B.reverse_edges(base, adj)
+    bridges, comps = B.repair(base, adj, entry, keep_local=1)
+    torch.cuda.synchronize()
+    return adj, entry, {"bridges": bridges, "components": comps}
+
+
+def gist_main(args, torch, B, synth, dev):
+    t0 = time.time()
+    w = synth.gist_like(n=args.n, nq=args.nq)
+    log(f"data {w.name}: {w.base.shape} + {w.queries.shape} queries in {time.time() - t0:.1f}s")
+    base = torch.from_numpy(w.base).to(dev)
+    queries = torch.from_numpy(w.queries).to(dev)
+    d, R, nq = w.base.shape[1], w.graph_R, args.nq
+    kq = w.info["k"].astype(np.int32)
+    Lq = np.maximum(w.info["L"], kq).astype(np.int32)
+    Mq = w.info["M"].astype(np.int32)
+    t0 = time.time()
+    adj, entry, ginfo = build_graph_logged(torch, B, base, w.graph_knn, R, w.graph_prune)
+    t_graph = time.time() - t0
+    log(f"graph built in {t_graph:.1f}s: entry {entry}, {ginfo}")
+    t0 = time.time()
+    gt, _ = B.knn(base, queries, int(kq.max()))
+    torch.cuda.synchronize()
+    log(f"ground truth (k={int(kq.max())}) in {time.time() - t0:.1f}s")
+
+    ix = B.Index(base, adj, entry)
+    bt = B.Batch(ix, Lq, kq, Mq, rho=0.8)
+    tuning = bt.tune(queries, reps=2)
+    log(f"tuning: {tuning}")
+    desc = bt.describe()
+    for c in desc["classes"]:
+        log(f"class M={c['M']} slots/lane={c['slots_per_lane']} queries={c['queries']} L_max={c['L_max']} "
+            f"stream={c['stream']}")
+
+    # one run with counters: recall and the bytes of the roofline
+    r = bt.run(queries, stats=True)
+    torch.cuda.synchronize()
+    ids = r.ids.cpu().numpy()
+    stats = r.stats.cpu().numpy()
+    gth = gt.cpu().numpy()
+    rec = np.array([np.isin(ids[q, :kq[q]], gth[q, :kq[q]]).mean() for q in range(nq)])
+    recall_by_k = {str(int(kk)): round(float(rec[kq == kk].mean()), 5) for kk in np.unique(kq)}
+    log(f"recall@k by k: {recall_by_k}, mean {rec.mean():.4f}")
+
+    # capture one run in a HIP graph and replay it
+    out = bt.outputs()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bt.run(queries, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bt.run(queries, out=out)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    written = np.arange(ids.shape[1])[None, :] < kq[:, None]
+    assert (out[0].cpu().numpy()[written] == ids[written]).all(), "graph replay differs from the eager run"
+    t_start = time.perf_counter()
+    launch_ms = timed_launches(torch, g.replay, args.steps)
+    wall = time.perf_counter() - t_start
+    ms_per_step = wall * 1e3 / args.steps
+    qps = nq / (ms_per_step / 1e3)
+    log(f"graph replay: {ms_per_step:.3f} ms per batch, {qps:,.0f} queries/s")
+
+    # the plain path: one search call per distinct (L, k, M), same results
+    groups = {}
+    for q in range(nq):
+        groups.setdefault((int(Lq[q]), int(kq[q]), int(Mq[q])), []).append(q)
+    gq = {key: torch.tensor(v, dtype=torch.int64, device=dev) for key, v in groups.items()}
+    gqueries = {key: queries.index_select(0, v).contiguous() for key, v in gq.items()}
+
+    def plain():
+        res = {}
+        for (L1, k1, M1), qv in gqueries.items():
+            res[(L1, k1, M1)] = ix.search(qv, k1, L1, M1, rho=0.8)
+        return res
+
+    res = plain()
+    torch.cuda.synchronize()
+    for (L1, k1, M1), rr in res.items():
+        sel = groups[(L1, k1, M1)]
+        assert (rr.ids.cpu().numpy() == ids[sel, :k1]).all(), "plain path and batch differ"
+    t1 = time.perf_counter()
+    ev = timed_launches(torch, plain, 1)
+    plain_ms = (time.perf_counter() - t1) * 1e3
+    log(f"plain path: {len(groups)} search calls, {plain_ms:.1f} ms wall, {ev[0]:.1f} ms on the stream")
+
+    D = stats[:, 3].astype(np.float64)
+    E = stats[:, 2].astype(np.float64)
+    bytes_launch = float((D * d * 4 + E * R * 4 + d * 4 + kq * 8).sum())
+    achieved = bytes_launch / (launch_ms.mean() / 1e3) / 1e9
+    t = stats.view(np.int64)[:, 3:5]
+    svc_ms = (t[:, 1] - t[:, 0]) / 1e5
+    res = {
+        "metric": "QPS of a mixed (L, k, M) batch in one captured HIP graph, recall@k vs exact, "
+                  "1M×960 GIST-shaped, 1 GPU",
+        "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {
+            "workload": f"gist-like {args.n}x{d} (128-component mixture, sigma 0.1), {nq} queries, L log-uniform "
+                        f"[32, 1024] raised to k, k in {{1, 10, 100}}, M in {{1, 4, 8}}, l2",
+            "graph": f"exact 64-NN, relative-neighbourhood prune to R={R}, repair (keep_local 1), medoid entry",
+            "graph_build_s": round(t_graph, 1), "sync": "adaptive", "rho": 0.8, "staged": True,
+            "recall_at_k_by_k": recall_by_k, "recall_mean": round(float(rec.mean()), 5),
+            "classes": desc["classes"], "tuning": tuning,
+            "plain_path": {"search_calls": len(groups), "ms_wall": round(plain_ms, 2),
+                           "ms_stream": round(float(ev[0]), 2),
+                           "qps": round(nq / (plain_ms / 1e3), 1)},
+            "p50_ms_in_batch": round(float(np.percentile(svc_ms, 50)), 4),
+            "p99_ms_in_batch": round(float(np.percentile(svc_ms, 99)), 4),
+            "flagged_queries": int(((stats[:, 5] & 3) != 0).sum()),
+        },
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "algorithmic_bytes_per_launch": round(bytes_launch),
+                     "kernel_ms": round(float(launch_ms.mean()), 4), "note": "one graph replay (all classes)"},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--nq", type=int, default=10_000)
+    ap.add_argument("--nq", type=int, default=0, help="queries (0: 10,000; 20,000 for gist)")
     ap.add_argument("--latency-queries", type=int, default=2000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--M", type=int, default=0, help="time this walker count only (0: sweep)")
     ap.add_argument("--L", type=int, default=0, help="with --M, time this L (0: sweep)")
     ap.add_argument("--sweep-json", default="")
-    ap.add_argument("--workload", choices=["sift", "deep"], default="sift")
+    ap.add_argument("--workload", choices=["sift", "deep", "gist"], default="sift")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run a plain elementwise copy of this many MiB (read and written "
                          "once) so that a profiler run can scale its byte counters")
@@ -266,8 +417,12 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     B.lib()
     dev = torch.device("cuda:0")
+    if args.nq <= 0:
+        args.nq = 20_000 if args.workload == "gist" else 10_000
     if args.workload == "deep":
         return deep_main(args, torch, B, synth, dev)
+    if args.workload == "gist":
+        return gist_main(args, torch, B, synth, dev)
 
     t0 = time.time()
     w = synth.sift_like(n=args.n, nq=args.nq)

@@ -149,3 +149,25 @@ def test_batch_errors(B, gist):
     bt = B.Batch(ix, L, k, M)
     with pytest.raises(B.SpeedAnnError, match="different number"):
         bt.run(dev(w.queries[:10]))
+
+
+def test_knn_gist_shaped(B):
+    # the exact kNN behind the GIST-shaped ground truth and graph: d = 960, k = 100
+    w = synth.gist_like(n=3000, nq=17)
+    print("case: knn gist-3000x960 k=100", flush=True)
+    ids, d = B.knn(dev(w.base), dev(w.queries), 100)
+    eids, ed = oracle.knn(w.base, w.queries, 100)
+    np.testing.assert_array_equal(host(ids), eids)
+    np.testing.assert_allclose(host(d), ed, rtol=1e-6)
+
+
+def test_chunked_graph_build_equals_library(B):
+    # bench.py builds the GIST-shaped graph in logged row chunks; it must equal sa_build_graph
+    import bench
+    w = synth.gist_like(n=5000, nq=1)
+    base = dev(w.base)
+    print("case: chunked graph build gist-5000x960 vs sa_build_graph", flush=True)
+    adj, entry, info = B.build_graph(base, 64, 32, "rng", True, keep_local=1)
+    adj2, entry2, info2 = bench.build_graph_logged(torch, B, base, 64, 32, "rng", chunk=1500)
+    assert entry == entry2 and info == info2
+    np.testing.assert_array_equal(host(adj), host(adj2))
