@@ -291,6 +291,67 @@ int sa_batch_set_config(sa_batch *batch, int32_t streams, int32_t lds_hash_slots
  * or a negative status. */
 int64_t sa_batch_describe(const sa_batch *batch, char *buf, size_t len);
 
+/* ------------------------------------------------------------------ serving
+ *
+ * A request loop over a resident index: requests (one query each, with its own k, L and
+ * M) are submitted from any host thread and served by a worker thread of the library
+ * with continuous batching.  Whenever one of `slots` micro-batch slots is free, the
+ * worker admits the waiting requests in arrival order into it, up to max_batch and
+ * while their visited-set regions (sized as sa_search sizes them for the request's
+ * register-queue size) fit the slot's share of workspace_bytes, and launches them on
+ * the slot's stream: one copy in, one launch per class of equal M and queue size, one
+ * copy out, an event.  Requests that arrive while micro-batches run are admitted into
+ * the next free slot, so their work overlaps on the device.  A request's result is the
+ * one sa_search gives for it alone, whatever it was batched with.  The worker owns all
+ * its device and pinned host memory, allocated at creation; the index must outlive
+ * the server. */
+typedef struct sa_server sa_server;
+
+typedef struct {
+    int32_t slots;            /* micro-batches in flight at once, 1..8 (default 4) */
+    int32_t max_batch;        /* requests per micro-batch, 1..65536 (default 1024) */
+    int32_t max_pending;      /* waiting requests held before submit reports SA_ECAPACITY (default 65536) */
+    int32_t k_max;            /* largest k a request may ask (default 100) */
+    size_t workspace_bytes;   /* device workspace for visited sets, split over the slots (default 1 GiB) */
+} sa_server_config;
+
+void sa_server_default_config(sa_server_config *cfg);
+
+/* params: NULL for defaults (shared by every request; rerank must be 0). */
+int sa_server_create(const sa_index *index, const sa_search_params *params, const sa_server_config *cfg,
+                     sa_server **out);
+
+/* Stops admitting, waits for the micro-batches in flight, frees everything.  Results
+ * not yet polled are dropped. */
+void sa_server_destroy(sa_server *server);
+
+/* Queues one request: query_host d float32 (copied before return), 1 <= k <= min(L,
+ * k_max), L <= 1024, 1 <= M <= 16; tag is returned with its result.  Thread-safe.
+ * SA_ECAPACITY when max_pending requests are already waiting. */
+int sa_server_submit(sa_server *server, const float *query_host, int32_t k, int32_t L, int32_t M, uint64_t tag);
+
+/* Takes up to max finished requests, waiting up to wait_us microseconds for the first:
+ * tags[i], ids (row i of stride ldo >= k_max: its first k entries), dists likewise,
+ * t_submit_ns / t_done_ns (steady-clock nanoseconds; either array may be NULL).
+ * Returns the count, or a negative status.  Thread-safe. */
+int32_t sa_server_poll(sa_server *server, int32_t max, uint64_t *tags, int32_t *ids, float *dists, int64_t ldo,
+                       int64_t *t_submit_ns, int64_t *t_done_ns, int32_t wait_us);
+
+/* Load replay: submits request i (queries_host row i, stride ldq; k[i], L[i], M[i]) at
+ * arrival_ns[i] nanoseconds after the call starts (non-decreasing), collects every
+ * result into row i of ids / dists (stride ldo) and latency_ns[i] = completion time -
+ * scheduled arrival, and returns the wall time from the first arrival to the last
+ * completion in *wall_ns.  Blocks until all n are done; requests submitted by others
+ * meanwhile are served too but not collected here. */
+int sa_server_replay(sa_server *server, const float *queries_host, int64_t n, int64_t ldq, const int32_t *k,
+                     const int32_t *L, const int32_t *M, const int64_t *arrival_ns, int32_t *ids, float *dists,
+                     int64_t ldo, int64_t *latency_ns, int64_t *wall_ns);
+
+/* Counters since creation: requests completed, micro-batches launched, kernel launches,
+ * largest micro-batch, and the sum of micro-batch sizes. */
+int sa_server_stats(const sa_server *server, int64_t *completed, int64_t *batches, int64_t *launches,
+                    int64_t *max_batch_seen, int64_t *sum_batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,13 +22,20 @@ QFLAG_MAX_STEPS, QFLAG_CAPACITY, QFLAG_SPILLED = 1, 2, 4
 EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_quantize", "sa_index_create_q", "sa_medoid", "sa_prune", "sa_reverse_edges",
            "sa_repair", "sa_build_graph", "sa_index_create", "sa_index_destroy", "sa_search_workspace_bytes", "sa_search",
            "sa_batch_create", "sa_batch_destroy", "sa_batch_workspace_bytes", "sa_batch_upload", "sa_batch_run",
-           "sa_batch_tune", "sa_batch_set_config", "sa_batch_describe"]
+           "sa_batch_tune", "sa_batch_set_config", "sa_batch_describe", "sa_server_default_config",
+           "sa_server_create", "sa_server_destroy", "sa_server_submit", "sa_server_poll", "sa_server_replay",
+           "sa_server_stats"]
 
 
 class SearchParams(C.Structure):
     _fields_ = [("sync", C.c_int32), ("static_I", C.c_int32), ("rho", C.c_double), ("staged", C.c_int32),
                 ("max_substeps", C.c_int32), ("lds_hash_slots", C.c_int32), ("ws_hash_slots", C.c_int32),
                 ("rerank", C.c_int32)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("max_batch", C.c_int32), ("max_pending", C.c_int32), ("k_max", C.c_int32),
+                ("workspace_bytes", C.c_size_t)]
 
 
 # sa_query_stats as a numpy/torch view: 6 int32 + 2 uint64 = 40 bytes
@@ -81,9 +88,20 @@ def lib():
         L.sa_batch_set_config.argtypes = [vp, i32, i32]
         L.sa_batch_describe.argtypes = [vp, C.c_char_p, sz]
         L.sa_batch_describe.restype = i64
+        L.sa_server_default_config.argtypes = [C.POINTER(ServerConfig)]
+        L.sa_server_default_config.restype = None
+        L.sa_server_create.argtypes = [vp, C.POINTER(SearchParams), C.POINTER(ServerConfig), C.POINTER(vp)]
+        L.sa_server_destroy.argtypes = [vp]
+        L.sa_server_destroy.restype = None
+        L.sa_server_submit.argtypes = [vp, vp, i32, i32, i32, C.c_uint64]
+        L.sa_server_poll.argtypes = [vp, i32, vp, vp, vp, i64, vp, vp, i32]
+        L.sa_server_poll.restype = i32
+        L.sa_server_replay.argtypes = [vp, vp, i64, i64, vp, vp, vp, vp, vp, vp, i64, vp, C.POINTER(C.c_int64)]
+        L.sa_server_stats.argtypes = [vp] + [C.POINTER(C.c_int64)] * 5
         for name in ("sa_knn", "sa_knn_ex", "sa_quantize", "sa_index_create_q", "sa_medoid", "sa_prune", "sa_reverse_edges", "sa_repair", "sa_build_graph", "sa_index_create",
                      "sa_search", "sa_batch_create", "sa_batch_upload", "sa_batch_run", "sa_batch_tune",
-                     "sa_batch_set_config"):
+                     "sa_batch_set_config", "sa_server_create", "sa_server_submit", "sa_server_replay",
+                     "sa_server_stats"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -394,3 +412,88 @@ class Batch:
         buf = C.create_string_buffer(n)
         lib().sa_batch_describe(self._h, buf, n)
         return json.loads(buf.value.decode())
+
+
+class Server:
+    """The serving loop (sa_server_*) over a resident Index: submit / poll from host
+    threads, or replay a timed arrival trace natively."""
+
+    def __init__(self, index: "Index", params: SearchParams | None = None, slots=None, max_batch=None,
+                 max_pending=None, k_max=None, workspace_bytes=None, **kw):
+        cfg = ServerConfig()
+        lib().sa_server_default_config(C.byref(cfg))
+        for name, v in (("slots", slots), ("max_batch", max_batch), ("max_pending", max_pending),
+                        ("k_max", k_max), ("workspace_bytes", workspace_bytes)):
+            if v is not None:
+                setattr(cfg, name, int(v))
+        self.cfg = cfg
+        self.index = index
+        if params is None:
+            params = make_params(**kw)
+        h = C.c_void_p()
+        _check(lib().sa_server_create(index._h, C.byref(params), C.byref(cfg), C.byref(h)), "sa_server_create")
+        self._h = h
+        self._lib = lib()
+        self.d = index.vec.shape[1]
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        L = getattr(self, "_lib", None)
+        if h is not None and h.value and L is not None:
+            L.sa_server_destroy(h)
+            self._h = None
+
+    __del__ = close
+
+    def _row(self, q):
+        import numpy as np
+        q = np.ascontiguousarray(q, dtype=np.float32).reshape(-1)
+        if q.shape[0] < self.d:
+            q = np.concatenate([q, np.zeros(self.d - q.shape[0], np.float32)])
+        return q
+
+    def submit(self, query, k: int, L: int, M: int, tag: int):
+        q = self._row(query)
+        _check(lib().sa_server_submit(self._h, q.ctypes.data, int(k), int(L), int(M), int(tag)), "sa_server_submit")
+
+    def poll(self, max_n=256, wait_us=1000):
+        """[(tag, ids, dists, t_submit_ns, t_done_ns)] of up to max_n finished requests."""
+        import numpy as np
+        km = self.cfg.k_max
+        tags = np.empty(max_n, np.uint64)
+        ids = np.empty((max_n, km), np.int32)
+        dists = np.empty((max_n, km), np.float32)
+        ts = np.empty(max_n, np.int64)
+        td = np.empty(max_n, np.int64)
+        n = lib().sa_server_poll(self._h, max_n, tags.ctypes.data, ids.ctypes.data, dists.ctypes.data, km,
+                                 ts.ctypes.data, td.ctypes.data, int(wait_us))
+        if n < 0:
+            _check(n, "sa_server_poll")
+        return [(int(tags[i]), ids[i], dists[i], int(ts[i]), int(td[i])) for i in range(n)]
+
+    def replay(self, queries, k, L, M, arrival_ns):
+        """Native load replay: returns (ids, dists, latency_ns, wall_ns); row i of ids has
+        its first k[i] entries."""
+        import numpy as np
+        q = np.ascontiguousarray(queries, dtype=np.float32)
+        if q.shape[1] < self.d:
+            q = np.ascontiguousarray(np.pad(q, ((0, 0), (0, self.d - q.shape[1]))))
+        n = q.shape[0]
+        ks = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (n,)))
+        Ls = np.ascontiguousarray(np.broadcast_to(np.asarray(L, np.int32), (n,)))
+        Ms = np.ascontiguousarray(np.broadcast_to(np.asarray(M, np.int32), (n,)))
+        arr = np.ascontiguousarray(arrival_ns, dtype=np.int64)
+        km = self.cfg.k_max
+        ids = np.full((n, km), -1, np.int32)
+        dists = np.full((n, km), np.inf, np.float32)
+        lat = np.zeros(n, np.int64)
+        wall = C.c_int64(0)
+        _check(lib().sa_server_replay(self._h, q.ctypes.data, n, q.shape[1], ks.ctypes.data, Ls.ctypes.data,
+                                      Ms.ctypes.data, arr.ctypes.data, ids.ctypes.data, dists.ctypes.data, km,
+                                      lat.ctypes.data, C.byref(wall)), "sa_server_replay")
+        return ids, dists, lat, int(wall.value)
+
+    def stats(self) -> dict:
+        v = [C.c_int64(0) for _ in range(5)]
+        _check(lib().sa_server_stats(self._h, *[C.byref(x) for x in v]), "sa_server_stats")
+        return dict(zip(["completed", "batches", "launches", "max_batch", "sum_batch"], [x.value for x in v]))

@@ -26,11 +26,7 @@ constexpr int MAX_STREAMS = 4;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int ni_bucket(int L)
-{
-    const int ni = (L + 63) / 64;
-    return ni <= 1 ? 1 : ni <= 2 ? 2 : ni <= 4 ? 4 : ni <= 6 ? 6 : ni <= 8 ? 8 : 16;
-}
+int ni_bucket(int L) { return queue_slots_bucket(L); }
 
 struct BatchClass {
     int32_t M, ni, Lmax, kmax;

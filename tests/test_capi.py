@@ -83,6 +83,16 @@ def test_validation_errors_without_device(B):
     p.rerank = 0
     assert L.sa_batch_create(ix, 3, None, bk.ctypes.data, bM.ctypes.data, C.byref(p), C.byref(bh)) == -1
     assert L.sa_batch_workspace_bytes(None) == 0
+    # serving: defaults and configuration checks before any device call
+    cfg = B.ServerConfig()
+    L.sa_server_default_config(C.byref(cfg))
+    assert (cfg.slots, cfg.max_batch, cfg.k_max) == (4, 1024, 100) and cfg.workspace_bytes == 1 << 30
+    sh = C.c_void_p(0)
+    cfg.slots = 9
+    assert L.sa_server_create(ix, None, C.byref(cfg), C.byref(sh)) == -1 and "slots" in _err(B)
+    cfg.slots, cfg.k_max = 2, 0
+    assert L.sa_server_create(ix, None, C.byref(cfg), C.byref(sh)) == -1 and "k_max" in _err(B)
+    assert L.sa_server_submit(None, fake, 10, 64, 1, 0) == -1
     assert L.sa_batch_describe(None, None, 0) < 0
     L.sa_index_destroy(ix)
     # exact kNN argument checks
