@@ -252,7 +252,8 @@ int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64
  * graph from hip_stream (the classes become parallel branches) and replayed.  The
  * workspace holds the uploaded per-query arrays and one visited-set region per query
  * (as sa_search sizes them for the class's largest L); the search regions are zero
- * between runs.  Re-rank (params->rerank != 0) is not supported in a batch. */
+ * between runs.  A re-rank (params->rerank != 0) runs after each class's search, as in
+ * sa_search, and needs the index's float32 vectors. */
 typedef struct sa_batch sa_batch;
 
 /* L, k, M: host arrays of nq entries, copied (1 <= k <= L <= 1024, 1 <= M <= 16).
@@ -317,7 +318,8 @@ typedef struct {
 
 void sa_server_default_config(sa_server_config *cfg);
 
-/* params: NULL for defaults (shared by every request; rerank must be 0). */
+/* params: NULL for defaults, shared by every request (a re-rank needs the index's
+ * float32 vectors). */
 int sa_server_create(const sa_index *index, const sa_search_params *params, const sa_server_config *cfg,
                      sa_server **out);
 

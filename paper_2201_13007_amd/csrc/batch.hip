@@ -158,7 +158,6 @@ int sa_batch_create(const sa_index *index, int64_t nq, const int32_t *L, const i
     sa_search_params p;
     if (params) p = *params;
     else sa_default_params(&p);
-    if (p.rerank != 0) return set_error(SA_EUNSUPPORTED, "a batch cannot re-rank (rerank must be 0)");
     int rc;
     for (int64_t q = 0; q < nq; ++q)
         if ((rc = check_search(index, 1, k[q], L[q], M[q], p)) != SA_OK)

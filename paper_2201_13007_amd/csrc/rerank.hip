@@ -18,9 +18,11 @@ struct RArgs {
     int64_t ldq;
     int32_t d, k;
     unsigned char *ws;
-    int64_t stride, list_off;   // bytes per query, and of its list within the region
+    int64_t stride, list_off;   // bytes per workspace region, and of the list within it
     int32_t *ids;
     float *dists;
+    const int32_t *order, *qk;  // batches: the query of region b, per-query k (null: b, k)
+    int64_t ldo;                // row stride of ids and dists
 };
 
 __device__ __forceinline__ uint64_t wave_min64(uint64_t v)
@@ -41,8 +43,10 @@ __global__ void __launch_bounds__(64) rerank_kernel(RArgs R)
     int32_t *const sid = reinterpret_cast<int32_t *>(nkey + 64);   // [64]
     float *const qs = reinterpret_cast<float *>(sid + 64);          // [16 LPV]
     const int lane = __lane_id();
-    const int64_t qi = blockIdx.x;
-    int32_t *const list = reinterpret_cast<int32_t *>(R.ws + qi * R.stride + R.list_off);
+    const int64_t job = blockIdx.x;
+    const int64_t qi = R.order ? R.order[job] : job;
+    const int kq = R.qk ? R.qk[qi] : R.k;
+    int32_t *const list = reinterpret_cast<int32_t *>(R.ws + job * R.stride + R.list_off);
     {
         const int nch = R.d >> 2;
         const float *qrow = R.queries + qi * R.ldq;
@@ -68,7 +72,7 @@ __global__ void __launch_bounds__(64) rerank_kernel(RArgs R)
         }
     }
     // the first k exact keys, one selection round each
-    for (int r = 0; r < R.k; ++r) {
+    for (int r = 0; r < kq; ++r) {
         uint64_t best = ek[0];
 #pragma unroll
         for (int i = 1; i < NI; ++i) best = ek[i] < best ? ek[i] : best;
@@ -76,8 +80,8 @@ __global__ void __launch_bounds__(64) rerank_kernel(RArgs R)
 #pragma unroll
         for (int i = 0; i < NI; ++i) ek[i] = ek[i] == best ? KEY_EMPTY : ek[i];
         if (lane == 0) {
-            R.ids[qi * R.k + r] = best == KEY_EMPTY ? -1 : key_id(best);
-            R.dists[qi * R.k + r] = best == KEY_EMPTY ? __builtin_inff() : key_dist(best);
+            R.ids[qi * R.ldo + r] = best == KEY_EMPTY ? -1 : key_id(best);
+            R.dists[qi * R.ldo + r] = best == KEY_EMPTY ? __builtin_inff() : key_dist(best);
         }
     }
     for (int j = lane; j <= nr; j += 64) list[j] = 0;   // leave the workspace zero-filled
@@ -107,9 +111,10 @@ hipError_t launch1_ni(const RArgs &R, bool l2, int L, int64_t nq, hipStream_t s)
 
 int launch_rerank(const float *vec32, int64_t ld32, const float *queries, int64_t ldq, int64_t nq, int32_t d,
                   int32_t metric, int32_t k, int32_t L, void *ws, int64_t stride, int64_t list_off, int32_t *ids,
-                  float *dists, hipStream_t s)
+                  float *dists, const int32_t *order, const int32_t *qk, int64_t ldo, hipStream_t s)
 {
-    RArgs R{vec32, ld32, queries, ldq, d, k, static_cast<unsigned char *>(ws), stride, list_off, ids, dists};
+    RArgs R{vec32, ld32, queries, ldq, d, k, static_cast<unsigned char *>(ws), stride, list_off, ids, dists,
+            order, qk, ldo > 0 ? ldo : k};
     const bool l2 = metric == SA_L2;
     hipError_t e;
     switch (lanes_per_vector(d)) {

@@ -130,7 +130,6 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     A.codes = a.codes; A.scale = a.scale; A.ldc = a.ldc; A.vec32 = a.vec32; A.ld32 = a.ld32; A.rerank = a.p.rerank;
     A.adj = a.adj; A.queries = a.queries; A.ldq = a.ldq;
     A.qL = a.qL; A.qk = a.qk; A.order = a.order; A.ldo = a.ldo > 0 ? a.ldo : a.k;
-    if (a.order && a.p.rerank != 0) return set_error(SA_EUNSUPPORTED, "a batch cannot re-rank");
     A.ids = a.ids; A.dists = a.dists; A.stats = a.stats;
     A.ghash = reinterpret_cast<unsigned long long *>(a.workspace);
     A.n = a.n;
@@ -158,7 +157,7 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     const int64_t stride = (int64_t)bytes_per_slot(a.M, llog2) << glog2;
     const int64_t list_off = ((int64_t)(compact ? 4 : 8) << glog2) + 4 * ((int64_t(1) << glog2) - 1025);
     return launch_rerank(a.vec32, a.ld32, a.queries, a.ldq, a.nq, a.d, a.metric, a.k, a.L, a.workspace, stride,
-                         list_off, a.ids, a.dists, stream);
+                         list_off, a.ids, a.dists, a.order, a.qk, A.ldo, stream);
 }
 
 }  // namespace sa

@@ -1009,7 +1009,7 @@ __device__ __forceinline__ void search_body(const KArgs &A)
 
 int launch_rerank(const float *vec32, int64_t ld32, const float *queries, int64_t ldq, int64_t nq, int32_t d,
                   int32_t metric, int32_t k, int32_t L, void *ws, int64_t stride, int64_t list_off, int32_t *ids,
-                  float *dists, hipStream_t s);
+                  float *dists, const int32_t *order, const int32_t *qk, int64_t ldo, hipStream_t s);
 int launch_search_single_f32(const search_detail::KArgs &A, int64_t nq, hipStream_t s);
 int launch_search_single_bf16(const search_detail::KArgs &A, int64_t nq, hipStream_t s);
 int launch_search_single_fp8(const search_detail::KArgs &A, int64_t nq, hipStream_t s);

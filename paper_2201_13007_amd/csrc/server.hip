@@ -312,7 +312,6 @@ int sa_server_create(const sa_index *index, const sa_search_params *params, cons
     sa_search_params p;
     if (params) p = *params;
     else sa_default_params(&p);
-    if (p.rerank != 0) return set_error(SA_EUNSUPPORTED, "the server does not re-rank (rerank must be 0)");
     int rc;
     if ((rc = check_search(index, 1, 1, 1024, 16, p)) != SA_OK) return rc;
     if ((rc = check_device()) != SA_OK) return rc;

@@ -78,8 +78,11 @@ def test_validation_errors_without_device(B):
     assert "query 1" in _err(B) and not bh.value
     p.rerank = -1
     bk[1] = 5
-    assert L.sa_batch_create(ix, 3, bL.ctypes.data, bk.ctypes.data, bM.ctypes.data, C.byref(p), C.byref(bh)) != 0
-    assert "re-rank" in _err(B)
+    qx = C.c_void_p(0)   # bf16 codes with no float32 vectors: nothing to re-rank with
+    assert L.sa_index_create_q(fake, 1, None, 32, None, 32, 100, 32, 0, fake, 16, 5, C.byref(qx)) == 0
+    assert L.sa_batch_create(qx, 3, bL.ctypes.data, bk.ctypes.data, bM.ctypes.data, C.byref(p), C.byref(bh)) != 0
+    assert "float32 vectors" in _err(B)
+    L.sa_index_destroy(qx)
     p.rerank = 0
     assert L.sa_batch_create(ix, 3, None, bk.ctypes.data, bM.ctypes.data, C.byref(p), C.byref(bh)) == -1
     assert L.sa_batch_workspace_bytes(None) == 0

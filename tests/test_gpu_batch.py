@@ -140,8 +140,6 @@ def test_batch_one_class_and_sift(B):
 def test_batch_errors(B, gist):
     w, adj, entry, L, k, M = gist
     ix = B.Index(dev(w.base), dev(adj), entry)
-    with pytest.raises(B.SpeedAnnError, match="re-rank"):
-        B.Batch(ix, L, k, M, rerank=-1)
     bad = k.copy()
     bad[5] = L[5] + 1
     with pytest.raises(B.SpeedAnnError, match="query 5"):
@@ -171,3 +169,24 @@ def test_chunked_graph_build_equals_library(B):
     adj2, entry2, info2 = bench.build_graph_logged(torch, B, base, 64, 32, "rng", chunk=1500)
     assert entry == entry2 and info == info2
     np.testing.assert_array_equal(host(adj), host(adj2))
+
+
+@pytest.mark.parametrize("rr", [-1, 30])
+def test_batch_rerank_bf16(B, rr):
+    # a re-ranked batch over bf16 codes equals sa_search with the same re-rank, per query
+    w = synth.deep_like(n=6000, nq=48)
+    adj, entry, _ = oracle.build_graph(w.base, 32, 24, "rng", do_repair=True, metric="ip")
+    rng = np.random.default_rng([2201, 13007, 79])
+    k = rng.choice(np.array([1, 10, 20], np.int32), size=48)
+    L = np.maximum(rng.integers(32, 200, size=48), 30).astype(np.int32)
+    M = rng.choice(np.array([1, 4], np.int32), size=48)
+    ix = B.Index(dev(w.base), dev(adj), entry, metric="ip", dtype="bf16")
+    q = dev(w.queries)
+    print(f"case: batch bf16 deep-6000 rerank={rr}", flush=True)
+    bt = B.Batch(ix, L, k, M, rerank=rr)
+    r = bt.run(q)
+    gi, gd = host(r.ids), host(r.dists)
+    for i in range(48):
+        a = ix.search(q[i:i + 1], int(k[i]), int(L[i]), int(M[i]), rerank=rr)
+        np.testing.assert_array_equal(gi[i, :k[i]], host(a.ids)[0], err_msg=f"query {i}")
+        np.testing.assert_array_equal(gd[i, :k[i]], host(a.dists)[0], err_msg=f"query {i}")

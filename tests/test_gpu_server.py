@@ -115,9 +115,26 @@ def test_server_errors(B, deep):
     ix = B.Index(dev(w.base), dev(adj), entry, metric="ip")
     with pytest.raises(B.SpeedAnnError, match="workspace_bytes"):
         B.Server(ix, workspace_bytes=1 << 16)
-    with pytest.raises(B.SpeedAnnError, match="re-rank"):
-        B.Server(ix, rerank=-1)
     srv = B.Server(ix, slots=1, max_batch=4, k_max=10, max_pending=2)
     with pytest.raises(B.SpeedAnnError, match="k_max"):
         srv.submit(w.queries[0], 20, 64, 1, 0)
+    srv.close()
+
+
+def test_server_rerank_bf16(B, deep):
+    w, adj, entry, k, L, M = deep
+    ix = B.Index(dev(w.base), dev(adj), entry, metric="ip", dtype="bf16")
+    q = dev(w.queries)
+    n = 64
+    want = []
+    for i in range(n):
+        r = ix.search(q[i:i + 1], int(k[i]), int(L[i]), int(M[i]), rerank=-1)
+        want.append((host(r.ids)[0], host(r.dists)[0]))
+    print("case: server bf16 with whole-list re-rank, 64 requests at 100k/s", flush=True)
+    srv = B.Server(ix, slots=4, max_batch=16, k_max=20, rerank=-1)
+    arrival = (np.arange(n) * 10_000).astype(np.int64)
+    ids, dists, lat, wall = srv.replay(w.queries[:n], k[:n], L[:n], M[:n], arrival)
+    for i in range(n):
+        np.testing.assert_array_equal(ids[i, :k[i]], want[i][0], err_msg=f"request {i}")
+        np.testing.assert_array_equal(dists[i, :k[i]], want[i][1], err_msg=f"request {i}")
     srv.close()
