@@ -296,20 +296,23 @@ int64_t sa_batch_describe(const sa_batch *batch, char *buf, size_t len);
  *
  * A request loop over a resident index: requests (one query each, with its own k, L and
  * M) are submitted from any host thread and served by a worker thread of the library
- * with continuous batching.  Whenever one of `slots` micro-batch slots is free, the
- * worker admits the waiting requests in arrival order into it, up to max_batch and
- * while their visited-set regions (sized as sa_search sizes them for the request's
- * register-queue size) fit the slot's share of workspace_bytes, and launches them on
- * the slot's stream: one copy in, one launch per class of equal M and queue size, one
- * copy out, an event.  Requests that arrive while micro-batches run are admitted into
- * the next free slot, so their work overlaps on the device.  A request's result is the
+ * with continuous batching.  Requests wait in one of up to four lanes by L (<= 128,
+ * <= 256, <= 512, above; fewer lanes if slots < 4), each with its own slots (slot s
+ * serves lane s mod lanes; every slot has a stream of its own).  Whenever a slot is free, the worker admits its
+ * lane's waiting requests in arrival order into it, up to max_batch and while their
+ * visited-set regions (sized as sa_search sizes them for the request's register-queue
+ * size) fit the slot's share of workspace_bytes, and launches them: one copy in, then
+ * per class of equal M and queue size, shortest first, a launch, the copy of its
+ * results and an event, after which its requests are complete.  Requests that arrive
+ * while micro-batches run are admitted into the next free slot, so their work overlaps
+ * on the device, and a short search never waits for a long one's slot.  A request's result is the
  * one sa_search gives for it alone, whatever it was batched with.  The worker owns all
  * its device and pinned host memory, allocated at creation; the index must outlive
  * the server. */
 typedef struct sa_server sa_server;
 
 typedef struct {
-    int32_t slots;            /* micro-batches in flight at once, 1..8 (default 4) */
+    int32_t slots;            /* micro-batches in flight at once, 1..16 (default 8) */
     int32_t max_batch;        /* requests per micro-batch, 1..65536 (default 1024) */
     int32_t max_pending;      /* waiting requests held before submit reports SA_ECAPACITY (default 65536) */
     int32_t k_max;            /* largest k a request may ask (default 100) */

@@ -2,13 +2,17 @@
 // micro-batch slots as they free up (continuous batching), and a load-replay helper.
 // Contracts are in include/speedann.h.
 //
-// A slot owns a stream, an event, pinned staging buffers in and out, device buffers
-// for the queries, the per-request (L, k) and the launch order, device result rows,
-// and its share of the workspace.  The worker loop: retire the slots whose event has
-// completed (results go to the completion queue), then fill every free slot from the
-// front of the waiting queue and launch it.  Requests are admitted strictly in arrival
-// order; a request whose visited-set region does not fit the slot's workspace waits
-// for the next slot.
+// Requests go to one of up to four lanes by L (<= 128, <= 256, <= 512, above), each with
+// its own waiting queue and slots (slot s serves lane s mod lanes), so that a short
+// search never waits behind a long one for a slot.  A slot owns a stream, pinned
+// staging buffers in and out, device buffers for the queries, the
+// per-request (L, k) and the result rows, its share of the workspace, and one event
+// per class.  Admission takes a lane's requests in arrival order (a request whose
+// visited-set region does not fit the slot's workspace waits for the next slot) and
+// stages them sorted by class, so that each class is a contiguous run of rows: classes
+// are launched shortest L first, each followed by the copy of its own result rows and
+// its own event, and the worker completes a class's requests as soon as its event has
+// passed.
 #include "sa_internal.h"
 
 #include <algorithm>
@@ -32,11 +36,15 @@ int64_t now_ns()
 
 size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
+constexpr int MAX_LANES = 4;
+
+int lane_index(int L) { return L <= 128 ? 0 : L <= 256 ? 1 : L <= 512 ? 2 : 3; }
+
 struct Request {
     uint64_t tag;
     int32_t k, L, M;
     int64_t t_submit;
-    int64_t ring;            // row of the query ring holding its vector
+    int32_t row;             // row of the query store holding its vector
     size_t region;           // workspace bytes reserved for it
 };
 
@@ -49,14 +57,31 @@ struct Done {
 };
 
 struct Slot {
+    int lane = 0;
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    std::vector<hipEvent_t> done;          // one per class, created as needed
+    std::vector<std::pair<int, int>> cls;  // row range of each class, in launch order
+    size_t next = 0;                       // first class not yet completed
     unsigned char *h_in = nullptr, *h_out = nullptr;
     unsigned char *d_in = nullptr, *d_out = nullptr, *d_ws = nullptr;
     size_t ws_bytes = 0;
-    std::vector<Request> reqs;
+    std::vector<Request> reqs;             // staged in class order
     bool busy = false;
 };
+
+// class order: walker count, register-queue size, then longest L first
+bool class_less(const Request &a, const Request &c)
+{
+    if (a.M != c.M) return a.M < c.M;
+    const int na = queue_slots_bucket(a.L), nc = queue_slots_bucket(c.L);
+    if (na != nc) return na < nc;
+    if (a.L != c.L) return a.L > c.L;
+    return a.t_submit < c.t_submit;
+}
+bool same_class(const Request &a, const Request &c)
+{
+    return a.M == c.M && queue_slots_bucket(a.L) == queue_slots_bucket(c.L);
+}
 
 }  // namespace
 }  // namespace sa
@@ -71,11 +96,14 @@ struct sa_server {
     int32_t d;
     std::vector<Slot> slots;
 
+    int nlanes;
+
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<Request> waiting;
-    std::vector<float> ring;     // max_pending rows of d floats
-    int64_t ring_tail = 0;       // next row to write (monotone; row = tail % max_pending)
+    std::deque<Request> waiting[MAX_LANES];
+    int64_t nwaiting = 0;
+    std::vector<float> store;     // max_pending rows of d floats holding waiting queries
+    std::vector<int32_t> free_rows;
     std::deque<Done> finished;
     bool stop = false;
     int error = SA_OK;
@@ -96,70 +124,73 @@ size_t request_region(const sa_server *S, int32_t L, int32_t M)
     return search_workspace_bytes(1, Lb, M, S->p, S->ix->R);
 }
 
-// Launches the requests of a filled slot: one copy in, one launch per class, one copy out.
+// Launches the requests of a filled slot (staged in class order): one copy in, then per
+// class, shortest first, its launch, the copy of its result rows and its event.
 int launch_slot(sa_server *S, Slot &sl)
 {
     const int b = (int)sl.reqs.size();
     const int d = S->d;
-    // layout of the staging buffers for b requests
-    const size_t o_q = 0, o_L = align16(4 * (size_t)b * d), o_k = o_L + align16(4 * (size_t)b),
-                 o_ord = o_k + align16(4 * (size_t)b), n_in = o_ord + 4 * (size_t)b;
+    const size_t o_L = align16(4 * (size_t)b * d), o_k = o_L + align16(4 * (size_t)b), n_in = o_k + 4 * (size_t)b;
     int32_t *hL = reinterpret_cast<int32_t *>(sl.h_in + o_L);
     int32_t *hk = reinterpret_cast<int32_t *>(sl.h_in + o_k);
-    int32_t *hord = reinterpret_cast<int32_t *>(sl.h_in + o_ord);
     for (int i = 0; i < b; ++i) {
         hL[i] = sl.reqs[i].L;
         hk[i] = sl.reqs[i].k;
-        hord[i] = i;
     }
-    // classes of equal M and queue size, longest L first within each
-    std::sort(hord, hord + b, [&](int32_t a, int32_t c) {
-        const Request &ra = sl.reqs[a], &rc = sl.reqs[c];
-        if (ra.M != rc.M) return ra.M < rc.M;
-        const int na = queue_slots_bucket(ra.L), nc = queue_slots_bucket(rc.L);
-        if (na != nc) return na < nc;
-        if (ra.L != rc.L) return ra.L > rc.L;
-        return a < c;
+    sl.cls.clear();
+    for (int i = 0; i < b;) {
+        int j = i + 1;
+        while (j < b && same_class(sl.reqs[j], sl.reqs[i])) ++j;
+        sl.cls.emplace_back(i, j);
+        i = j;
+    }
+    // shortest class first: its requests complete before the long ones start
+    std::stable_sort(sl.cls.begin(), sl.cls.end(), [&](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+        return sl.reqs[x.first].L < sl.reqs[y.first].L;
     });
+    while (sl.done.size() < sl.cls.size()) {
+        hipEvent_t e;
+        SA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        sl.done.push_back(e);
+    }
     SA_HIP(hipMemcpyAsync(sl.d_in, sl.h_in, n_in, hipMemcpyHostToDevice, sl.stream));
     const int kmax = S->cfg.k_max;
     int32_t *d_ids = reinterpret_cast<int32_t *>(sl.d_out);
     float *d_dists = reinterpret_cast<float *>(sl.d_out + 4 * (size_t)S->cfg.max_batch * kmax);
+    int32_t *h_ids = reinterpret_cast<int32_t *>(sl.h_out);
+    float *h_dists = reinterpret_cast<float *>(sl.h_out + 4 * (size_t)S->cfg.max_batch * kmax);
     const sa_index *ix = S->ix;
     size_t ws_off = 0;
-    for (int i = 0; i < b;) {
-        const Request &r0 = sl.reqs[hord[i]];
-        const int M = r0.M, nb = queue_slots_bucket(r0.L), Lmax = r0.L;
-        int j = i, kc = 1;
-        while (j < b && sl.reqs[hord[j]].M == M && queue_slots_bucket(sl.reqs[hord[j]].L) == nb) {
-            kc = std::max(kc, sl.reqs[hord[j]].k);
-            ++j;
-        }
+    for (size_t c = 0; c < sl.cls.size(); ++c) {
+        const int i = sl.cls[c].first, j = sl.cls[c].second;
+        const Request &r0 = sl.reqs[i];   // the longest L of its class
+        int kc = 1;
+        for (int t = i; t < j; ++t) kc = std::max(kc, sl.reqs[t].k);
         SearchLaunch a;
         a.codes = ix->codes; a.scale = ix->scale; a.ldc = ix->ldc; a.dtype = ix->dtype;
         a.vec32 = ix->vec32; a.ld32 = ix->ld32;
         a.n = ix->n; a.d = ix->d; a.metric = ix->metric;
         a.adj = ix->adj; a.R = ix->R; a.entry = ix->entry;
-        a.queries = reinterpret_cast<const float *>(sl.d_in + o_q); a.ldq = d;
-        a.nq = j - i; a.k = kc; a.L = Lmax; a.M = M; a.p = S->p;
-        a.ids = d_ids; a.dists = d_dists; a.stats = nullptr;
-        const size_t region = search_workspace_bytes(1, Lmax, M, S->p, ix->R);
+        // the class's rows: query q of the launch is staged row i + q
+        a.queries = reinterpret_cast<const float *>(sl.d_in) + (size_t)i * d; a.ldq = d;
+        a.nq = j - i; a.k = kc; a.L = r0.L; a.M = r0.M; a.p = S->p;
+        a.ids = d_ids + (size_t)i * kmax; a.dists = d_dists + (size_t)i * kmax; a.stats = nullptr;
+        const size_t region = search_workspace_bytes(1, r0.L, r0.M, S->p, ix->R);
         a.workspace = sl.d_ws + ws_off; a.ws_bytes = region * (size_t)(j - i);
         ws_off += (a.ws_bytes + 255) & ~size_t(255);
-        a.qL = reinterpret_cast<const int32_t *>(sl.d_in + o_L);
-        a.qk = reinterpret_cast<const int32_t *>(sl.d_in + o_k);
-        a.order = reinterpret_cast<const int32_t *>(sl.d_in + o_ord) + i;
+        a.qL = reinterpret_cast<const int32_t *>(sl.d_in + o_L) + i;
+        a.qk = reinterpret_cast<const int32_t *>(sl.d_in + o_k) + i;
+        a.order = nullptr;
         a.ldo = kmax;
         const int rc = launch_search(a, sl.stream);
         if (rc != SA_OK) return rc;
+        const size_t rows = 4 * (size_t)(j - i) * kmax;
+        SA_HIP(hipMemcpyAsync(h_ids + (size_t)i * kmax, a.ids, rows, hipMemcpyDeviceToHost, sl.stream));
+        SA_HIP(hipMemcpyAsync(h_dists + (size_t)i * kmax, a.dists, rows, hipMemcpyDeviceToHost, sl.stream));
+        SA_HIP(hipEventRecord(sl.done[c], sl.stream));
         S->launches.fetch_add(1, std::memory_order_relaxed);
-        i = j;
     }
-    const size_t rows = 4 * (size_t)b * kmax;
-    SA_HIP(hipMemcpyAsync(sl.h_out, d_ids, rows, hipMemcpyDeviceToHost, sl.stream));
-    SA_HIP(hipMemcpyAsync(sl.h_out + 4 * (size_t)S->cfg.max_batch * kmax, d_dists, rows, hipMemcpyDeviceToHost,
-                          sl.stream));
-    SA_HIP(hipEventRecord(sl.done, sl.stream));
+    sl.next = 0;
     sl.busy = true;
     S->batches.fetch_add(1, std::memory_order_relaxed);
     S->sum_batch.fetch_add(b, std::memory_order_relaxed);
@@ -169,30 +200,30 @@ int launch_slot(sa_server *S, Slot &sl)
     return SA_OK;
 }
 
-void retire_slot(sa_server *S, Slot &sl)
+// Completes the requests of class c of a slot.
+void retire_class(sa_server *S, Slot &sl, size_t c)
 {
     const int64_t t = now_ns();
     const int kmax = S->cfg.k_max;
     const int32_t *ids = reinterpret_cast<const int32_t *>(sl.h_out);
     const float *dists = reinterpret_cast<const float *>(sl.h_out + 4 * (size_t)S->cfg.max_batch * kmax);
-    std::vector<Done> out(sl.reqs.size());
-    for (size_t i = 0; i < sl.reqs.size(); ++i) {
+    const int i0 = sl.cls[c].first, i1 = sl.cls[c].second;
+    std::vector<Done> out(i1 - i0);
+    for (int i = i0; i < i1; ++i) {
         const Request &r = sl.reqs[i];
-        Done &o = out[i];
+        Done &o = out[i - i0];
         o.tag = r.tag;
         o.k = r.k;
         o.t_submit = r.t_submit;
         o.t_done = t;
-        o.ids.assign(ids + i * kmax, ids + i * kmax + r.k);
-        o.dists.assign(dists + i * kmax, dists + i * kmax + r.k);
+        o.ids.assign(ids + (size_t)i * kmax, ids + (size_t)i * kmax + r.k);
+        o.dists.assign(dists + (size_t)i * kmax, dists + (size_t)i * kmax + r.k);
     }
     {
         std::lock_guard<std::mutex> g(S->mu);
         for (Done &o : out) S->finished.push_back(std::move(o));
     }
-    S->completed.fetch_add((int64_t)sl.reqs.size(), std::memory_order_relaxed);
-    sl.reqs.clear();
-    sl.busy = false;
+    S->completed.fetch_add(i1 - i0, std::memory_order_relaxed);
     S->cv_done.notify_all();
 }
 
@@ -205,21 +236,28 @@ void worker_main(sa_server *S)
         S->cv_done.notify_all();
         return;
     }
-    const int64_t maxp = S->cfg.max_pending;
     for (;;) {
         bool progressed = false, any_busy = false;
         for (Slot &sl : S->slots) {
             if (!sl.busy) continue;
-            const hipError_t q = hipEventQuery(sl.done);
-            if (q == hipSuccess) {
-                retire_slot(S, sl);
+            // classes complete in launch order on the slot's stream
+            while (sl.next < sl.cls.size()) {
+                const hipError_t q = hipEventQuery(sl.done[sl.next]);
+                if (q == hipErrorNotReady) break;
+                if (q != hipSuccess) {
+                    std::lock_guard<std::mutex> g(S->mu);
+                    S->error = hip_fail(q, "serving micro-batch");
+                    S->stop = true;
+                    break;
+                }
+                retire_class(S, sl, sl.next++);
                 progressed = true;
-            } else if (q == hipErrorNotReady) {
-                any_busy = true;
+            }
+            if (sl.next >= sl.cls.size() || S->error != SA_OK) {
+                sl.reqs.clear();
+                sl.busy = false;
             } else {
-                std::lock_guard<std::mutex> g(S->mu);
-                S->error = hip_fail(q, "serving micro-batch");
-                S->stop = true;
+                any_busy = true;
             }
         }
         // fill free slots from the front of the waiting queue
@@ -227,17 +265,24 @@ void worker_main(sa_server *S)
             if (sl.busy) continue;
             {
                 std::lock_guard<std::mutex> g(S->mu);
-                if (S->waiting.empty() || S->error != SA_OK) break;
+                if (S->error != SA_OK) break;
+                std::deque<Request> &wq = S->waiting[sl.lane];
+                if (wq.empty()) continue;
                 size_t used = 0;
                 float *hq = reinterpret_cast<float *>(sl.h_in);
-                while (!S->waiting.empty() && (int)sl.reqs.size() < S->cfg.max_batch) {
-                    const Request &r = S->waiting.front();
+                while (!wq.empty() && (int)sl.reqs.size() < S->cfg.max_batch) {
+                    const Request &r = wq.front();
                     if (used + r.region > sl.ws_bytes && !sl.reqs.empty()) break;
-                    std::memcpy(hq + sl.reqs.size() * S->d, S->ring.data() + (r.ring % maxp) * S->d,
-                                4 * (size_t)S->d);
                     used += r.region;
                     sl.reqs.push_back(r);
-                    S->waiting.pop_front();
+                    wq.pop_front();
+                    --S->nwaiting;
+                }
+                // stage in class order, then give the store rows back
+                std::sort(sl.reqs.begin(), sl.reqs.end(), class_less);
+                for (size_t i = 0; i < sl.reqs.size(); ++i) {
+                    std::memcpy(hq + i * S->d, S->store.data() + (size_t)sl.reqs[i].row * S->d, 4 * (size_t)S->d);
+                    S->free_rows.push_back(sl.reqs[i].row);
                 }
             }
             S->cv_work.notify_all();   // room in the waiting queue
@@ -253,7 +298,7 @@ void worker_main(sa_server *S)
             any_busy = true;
         }
         std::unique_lock<std::mutex> lk(S->mu);
-        if (S->stop && !any_busy && (S->waiting.empty() || S->error != SA_OK)) break;
+        if (S->stop && !any_busy && (S->nwaiting == 0 || S->error != SA_OK)) break;
         if (progressed) continue;
         if (any_busy) {
             // micro-batches on the device: poll their events again shortly
@@ -261,7 +306,7 @@ void worker_main(sa_server *S)
             std::this_thread::yield();
         } else {
             S->cv_work.wait_for(lk, std::chrono::microseconds(500),
-                                [&] { return S->stop || !S->waiting.empty(); });
+                                [&] { return S->stop || S->nwaiting > 0; });
         }
     }
     S->cv_done.notify_all();
@@ -271,7 +316,7 @@ void free_server(sa_server *S)
 {
     for (Slot &sl : S->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        if (sl.done) (void)hipEventDestroy(sl.done);
+        for (hipEvent_t e : sl.done) (void)hipEventDestroy(e);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.h_in) (void)hipHostFree(sl.h_in);
         if (sl.h_out) (void)hipHostFree(sl.h_out);
@@ -289,7 +334,7 @@ extern "C" {
 void sa_server_default_config(sa_server_config *cfg)
 {
     if (!cfg) return;
-    cfg->slots = 4;
+    cfg->slots = 8;
     cfg->max_batch = 1024;
     cfg->max_pending = 65536;
     cfg->k_max = 100;
@@ -305,7 +350,7 @@ int sa_server_create(const sa_index *index, const sa_search_params *params, cons
     sa_server_config c;
     if (cfg) c = *cfg;
     else sa_server_default_config(&c);
-    if (c.slots < 1 || c.slots > 8) return set_error(SA_EINVAL, "slots=%d must be in [1, 8]", c.slots);
+    if (c.slots < 1 || c.slots > 16) return set_error(SA_EINVAL, "slots=%d must be in [1, 16]", c.slots);
     if (c.max_batch < 1 || c.max_batch > 65536) return set_error(SA_EINVAL, "max_batch must be in [1, 65536]");
     if (c.max_pending < 1) return set_error(SA_EINVAL, "max_pending must be >= 1");
     if (c.k_max < 1 || c.k_max > 1024) return set_error(SA_EINVAL, "k_max must be in [1, 1024]");
@@ -330,13 +375,17 @@ int sa_server_create(const sa_index *index, const sa_search_params *params, cons
         delete S;
         return set_error(SA_EINVAL, "workspace_bytes must be at least %zu (one L=1024, M=16 request per slot)", need);
     }
-    S->ring.resize((size_t)c.max_pending * S->d);
+    S->store.resize((size_t)c.max_pending * S->d);
+    S->free_rows.resize(c.max_pending);
+    for (int32_t i = 0; i < c.max_pending; ++i) S->free_rows[i] = c.max_pending - 1 - i;
+    S->nlanes = std::min(MAX_LANES, c.slots);
     S->slots.resize(c.slots);
     hipError_t e = hipSuccess;
-    for (Slot &sl : S->slots) {
+    for (size_t si = 0; si < S->slots.size(); ++si) {
+        Slot &sl = S->slots[si];
+        sl.lane = (int)(si % S->nlanes);
         sl.ws_bytes = per_slot & ~size_t(255);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_in), in_bytes(S), hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_out), out_bytes(S), hipHostMallocDefault);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.d_in), in_bytes(S));
@@ -361,7 +410,8 @@ void sa_server_destroy(sa_server *S)
     {
         std::lock_guard<std::mutex> g(S->mu);
         S->stop = true;
-        S->waiting.clear();
+        for (int l = 0; l < MAX_LANES; ++l) S->waiting[l].clear();
+        S->nwaiting = 0;
     }
     S->cv_work.notify_all();
     if (S->worker.joinable()) S->worker.join();
@@ -385,12 +435,14 @@ int sa_server_submit(sa_server *S, const float *query_host, int32_t k, int32_t L
         std::lock_guard<std::mutex> g(S->mu);
         if (S->error != SA_OK) return set_error(S->error, "the server stopped after an error");
         if (S->stop) return set_error(SA_EINVAL, "the server is stopping");
-        if ((int64_t)S->waiting.size() >= S->cfg.max_pending)
+        if (S->free_rows.empty())
             return set_error(SA_ECAPACITY, "%d requests are already waiting", S->cfg.max_pending);
-        r.ring = S->ring_tail++;
-        std::memcpy(S->ring.data() + (r.ring % S->cfg.max_pending) * S->d, query_host, 4 * (size_t)S->d);
+        r.row = S->free_rows.back();
+        S->free_rows.pop_back();
+        std::memcpy(S->store.data() + (size_t)r.row * S->d, query_host, 4 * (size_t)S->d);
         r.t_submit = now_ns();
-        S->waiting.push_back(r);
+        S->waiting[std::min(lane_index(L), S->nlanes - 1)].push_back(r);
+        ++S->nwaiting;
     }
     S->cv_work.notify_one();
     return SA_OK;

@@ -89,9 +89,9 @@ def test_validation_errors_without_device(B):
     # serving: defaults and configuration checks before any device call
     cfg = B.ServerConfig()
     L.sa_server_default_config(C.byref(cfg))
-    assert (cfg.slots, cfg.max_batch, cfg.k_max) == (4, 1024, 100) and cfg.workspace_bytes == 1 << 30
+    assert (cfg.slots, cfg.max_batch, cfg.k_max) == (8, 1024, 100) and cfg.workspace_bytes == 1 << 30
     sh = C.c_void_p(0)
-    cfg.slots = 9
+    cfg.slots = 17
     assert L.sa_server_create(ix, None, C.byref(cfg), C.byref(sh)) == -1 and "slots" in _err(B)
     cfg.slots, cfg.k_max = 2, 0
     assert L.sa_server_create(ix, None, C.byref(cfg), C.byref(sh)) == -1 and "k_max" in _err(B)
