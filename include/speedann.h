@@ -237,6 +237,40 @@ int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64
               int32_t M, const sa_search_params *params, int32_t *ids_dev, float *dists_dev,
               sa_query_stats *stats_dev, void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* ------------------------------------------------------------------ renumbering
+ *
+ * The GPU counterpart of the neighbour grouping of Sec. 4.4: renumber the vertices so
+ * that vertices a search meets together sit together in memory.  An index built over
+ * the permuted vectors and graph, with sa_index_set_id_map(perm), returns ids in the
+ * original numbering; its searches are the searches of the renumbered graph (equal
+ * distances are ordered by the new ids). */
+typedef enum {
+    SA_ORDER_DEGREE = 0,   /* in-degree descending, ties by id */
+    SA_ORDER_BFS = 1       /* breadth-first from entry, neighbours in row order; unreachable vertices last, by id */
+} sa_order;
+
+/* perm_dev (n int32, device) gets the order: perm[i] = original id of new vertex i.
+ * adj_dev: n x R int32 (-1 padded).  Offline step: counts on the device, orders on the
+ * host; synchronous; allocates temporaries. */
+int sa_graph_order(const int32_t *adj_dev, int64_t n, int32_t R, int32_t entry, int32_t mode, int32_t *perm_dev,
+                   void *hip_stream);
+
+/* dst row i = src row perm[i], rows of row_bytes (a multiple of 4) for vectors or codes;
+ * a perm entry outside [0, n) gives a zero row.  src and dst must differ.  Enqueued. */
+int sa_permute_rows(const void *src_dev, int64_t n, int64_t row_bytes, const int32_t *perm_dev, void *dst_dev,
+                    void *hip_stream);
+
+/* adj_out row i = adj row perm[i] with ids renumbered through inv (written to inv_dev,
+ * n int32: inv[perm[i]] = i); the entry of the new graph is inv[entry].  adj and adj_out
+ * must differ.  Enqueued. */
+int sa_permute_graph(const int32_t *adj_dev, int64_t n, int32_t R, const int32_t *perm_dev, int32_t *inv_dev,
+                     int32_t *adj_out_dev, void *hip_stream);
+
+/* Result ids of every later search on index go through id_map_dev (n int32, device,
+ * borrowed; NULL to stop): a small kernel after the search maps them on the same
+ * stream. */
+int sa_index_set_id_map(sa_index *index, const int32_t *id_map_dev);
+
 /* ------------------------------------------------------------------ batches
  *
  * A batch is a fixed set of nq queries, each with its own L, k and M, searched together:

@@ -275,3 +275,43 @@ def rerank(base, queries, cand, k, metric="l2"):
     lib().or_rerank(base, base.shape[1], base.shape[1], _metric(metric), queries, nq, queries.shape[1], cand, L, k,
                     ids, dists)
     return ids, dists
+
+
+def graph_order(adj, entry, mode="bfs"):
+    """Vertex renumbering (the GPU counterpart of the neighbour grouping of Sec. 4.4):
+    perm[i] = original id of new vertex i.  "degree": in-degree descending, equal
+    in-degrees by id.  "bfs": breadth-first from entry, neighbours in row order, every
+    vertex taken when first seen; unreachable vertices after, by id.  Plain Python."""
+    adj = np.asarray(adj)
+    n = adj.shape[0]
+    if mode == "degree":
+        indeg = np.zeros(n, np.int64)
+        for row in adj:
+            for u in row:
+                if 0 <= u < n:
+                    indeg[u] += 1
+        return np.array(sorted(range(n), key=lambda v: (-indeg[v], v)), np.int32)
+    seen = [False] * n
+    order = [int(entry)]
+    seen[entry] = True
+    head = 0
+    while head < len(order):
+        for u in adj[order[head]]:
+            u = int(u)
+            if 0 <= u < n and not seen[u]:
+                seen[u] = True
+                order.append(u)
+        head += 1
+    order += [v for v in range(n) if not seen[v]]
+    return np.array(order, np.int32)
+
+
+def permute(base, adj, entry, perm):
+    """The index in the new numbering: rows base[perm[i]], adjacency rows adj[perm[i]]
+    with every id u replaced by its new id, and the new entry."""
+    perm = np.asarray(perm, np.int64)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    a = np.asarray(adj)[perm]
+    a2 = np.where(a >= 0, inv[np.maximum(a, 0)], -1).astype(np.int32)
+    return np.ascontiguousarray(np.asarray(base)[perm]), a2, int(inv[entry])

@@ -24,7 +24,7 @@ EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_quan
            "sa_batch_create", "sa_batch_destroy", "sa_batch_workspace_bytes", "sa_batch_upload", "sa_batch_run",
            "sa_batch_tune", "sa_batch_set_config", "sa_batch_describe", "sa_server_default_config",
            "sa_server_create", "sa_server_destroy", "sa_server_submit", "sa_server_poll", "sa_server_replay",
-           "sa_server_stats"]
+           "sa_server_stats", "sa_graph_order", "sa_permute_rows", "sa_permute_graph", "sa_index_set_id_map"]
 
 
 class SearchParams(C.Structure):
@@ -98,10 +98,15 @@ def lib():
         L.sa_server_poll.restype = i32
         L.sa_server_replay.argtypes = [vp, vp, i64, i64, vp, vp, vp, vp, vp, vp, i64, vp, C.POINTER(C.c_int64)]
         L.sa_server_stats.argtypes = [vp] + [C.POINTER(C.c_int64)] * 5
+        L.sa_graph_order.argtypes = [vp, i64, i32, i32, i32, vp, vp]
+        L.sa_permute_rows.argtypes = [vp, i64, i64, vp, vp, vp]
+        L.sa_permute_graph.argtypes = [vp, i64, i32, vp, vp, vp, vp]
+        L.sa_index_set_id_map.argtypes = [vp, vp]
         for name in ("sa_knn", "sa_knn_ex", "sa_quantize", "sa_index_create_q", "sa_medoid", "sa_prune", "sa_reverse_edges", "sa_repair", "sa_build_graph", "sa_index_create",
                      "sa_search", "sa_batch_create", "sa_batch_upload", "sa_batch_run", "sa_batch_tune",
                      "sa_batch_set_config", "sa_server_create", "sa_server_submit", "sa_server_replay",
-                     "sa_server_stats"):
+                     "sa_server_stats", "sa_graph_order", "sa_permute_rows", "sa_permute_graph",
+                     "sa_index_set_id_map"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -278,9 +283,10 @@ class Index:
     """A graph index over device arrays (borrowed: keep vec and adj alive)."""
 
     def __init__(self, vec: torch.Tensor, adj: torch.Tensor, entry: int, metric="l2", dtype="f32", codes=None,
-                 scale=None):
+                 scale=None, id_map: torch.Tensor | None = None):
         """vec: float32 vectors.  dtype "bf16" / "fp8": the search reads codes and scale (from
-        quantize(vec, dtype), made here when not given) and vec serves the re-rank."""
+        quantize(vec, dtype), made here when not given) and vec serves the re-rank.
+        id_map: for a renumbered index (reorder), new id -> original id of the results."""
         vec = pad_dim(_mat(vec, "vectors"))
         if adj.dtype != torch.int32 or not adj.is_cuda or not adj.is_contiguous():
             raise SpeedAnnError("adj must be a contiguous int32 device tensor")
@@ -300,6 +306,11 @@ class Index:
         self._h = h
         self._ws = None
         self._lib = lib()   # kept for __del__, which may run after module teardown
+        self.id_map = id_map
+        if id_map is not None:
+            if id_map.dtype != torch.int32 or not id_map.is_cuda or id_map.numel() != vec.shape[0]:
+                raise SpeedAnnError("id_map must be an int32 device tensor of n entries")
+            _check(lib().sa_index_set_id_map(h, id_map.data_ptr()), "sa_index_set_id_map")
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -497,3 +508,43 @@ class Server:
         v = [C.c_int64(0) for _ in range(5)]
         _check(lib().sa_server_stats(self._h, *[C.byref(x) for x in v]), "sa_server_stats")
         return dict(zip(["completed", "batches", "launches", "max_batch", "sum_batch"], [x.value for x in v]))
+
+
+ORDERS = {"degree": 0, "bfs": 1}
+
+
+def graph_order(adj: torch.Tensor, entry: int, mode="bfs", stream=None) -> torch.Tensor:
+    """perm (int32, device): perm[i] = original id of new vertex i (sa_graph_order)."""
+    assert adj.dtype == torch.int32 and adj.is_contiguous() and adj.is_cuda
+    perm = torch.empty(adj.shape[0], dtype=torch.int32, device=adj.device)
+    _check(lib().sa_graph_order(adj.data_ptr(), adj.shape[0], adj.shape[1], int(entry), ORDERS[mode],
+                                perm.data_ptr(), _stream(stream)), "sa_graph_order")
+    return perm
+
+
+def permute_rows(src: torch.Tensor, perm: torch.Tensor, stream=None) -> torch.Tensor:
+    src = src.contiguous()
+    dst = torch.empty_like(src)
+    row_bytes = src.element_size() * (src.numel() // max(1, src.shape[0]))
+    _check(lib().sa_permute_rows(src.data_ptr(), src.shape[0], row_bytes, perm.data_ptr(), dst.data_ptr(),
+                                 _stream(stream)), "sa_permute_rows")
+    return dst
+
+
+def permute_graph(adj: torch.Tensor, perm: torch.Tensor, stream=None):
+    """(adj in the new numbering, inv) with inv[perm[i]] = i."""
+    out = torch.empty_like(adj)
+    inv = torch.empty_like(perm)
+    _check(lib().sa_permute_graph(adj.data_ptr(), adj.shape[0], adj.shape[1], perm.data_ptr(), inv.data_ptr(),
+                                  out.data_ptr(), _stream(stream)), "sa_permute_graph")
+    return out, inv
+
+
+def reorder(base: torch.Tensor, adj: torch.Tensor, entry: int, mode="bfs"):
+    """(base, adj, entry, perm) of the renumbered index; an Index over them built with
+    id_map=perm returns original ids."""
+    perm = graph_order(adj, entry, mode)
+    base2 = permute_rows(pad_dim(_mat(base, "base")), perm)
+    adj2, inv = permute_graph(adj, perm)
+    torch.cuda.synchronize()
+    return base2, adj2, int(inv[entry].item()), perm

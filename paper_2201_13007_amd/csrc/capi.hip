@@ -291,7 +291,7 @@ int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64
     a.codes = index->codes; a.scale = index->scale; a.ldc = index->ldc; a.dtype = index->dtype;
     a.vec32 = index->vec32; a.ld32 = index->ld32;
     a.n = index->n; a.d = index->d; a.metric = index->metric;
-    a.adj = index->adj; a.R = index->R; a.entry = index->entry;
+    a.adj = index->adj; a.R = index->R; a.entry = index->entry; a.id_map = index->id_map;
     a.queries = queries_dev; a.ldq = ldq; a.nq = nq; a.k = k; a.L = L; a.M = M; a.p = p;
     a.ids = ids_dev; a.dists = dists_dev; a.stats = stats_dev; a.workspace = workspace; a.ws_bytes = ws_bytes;
     return launch_search(a, (hipStream_t)hip_stream);

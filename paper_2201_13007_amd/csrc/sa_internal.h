@@ -87,7 +87,12 @@ struct SearchLaunch {
     // runs; L above is then the largest L and nq the number of workgroups
     const int32_t *qL = nullptr, *qk = nullptr, *order = nullptr;
     int64_t ldo = 0;       // row stride of ids and dists (0: k)
+    const int32_t *id_map = nullptr;   // result ids go through it (a renumbered index)
 };
+
+// ids of each job's first k (or qk[q]) results replaced by id_map[id]; enqueued only
+int launch_map_ids(int32_t *ids, int64_t ldo, int64_t njobs, int32_t k, const int32_t *order, const int32_t *qk,
+                   const int32_t *id_map, int64_t n, hipStream_t s);
 
 int launch_quantize(const float *x, int64_t n, int32_t d, int64_t ld, int32_t dtype, void *codes, int64_t ldc,
                     float *scale, hipStream_t stream);
@@ -126,4 +131,5 @@ struct sa_index {
     int32_t d, metric;
     const int32_t *adj;
     int32_t R, entry;
+    const int32_t *id_map = nullptr;   // new id -> original id, for renumbered indexes
 };

@@ -152,12 +152,15 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
         else if (a.dtype == SA_FP8E4M3) rc = launch_search_multi_fp8(A, a.nq, a.M, Y.total, stream);
         else rc = launch_search_multi_f32(A, a.nq, a.M, Y.total, stream);
     }
-    if (rc != SA_OK || a.p.rerank == 0) return rc;
-    // the list sits at the end of the slot list, which follows the table in each region
-    const int64_t stride = (int64_t)bytes_per_slot(a.M, llog2) << glog2;
-    const int64_t list_off = ((int64_t)(compact ? 4 : 8) << glog2) + 4 * ((int64_t(1) << glog2) - 1025);
-    return launch_rerank(a.vec32, a.ld32, a.queries, a.ldq, a.nq, a.d, a.metric, a.k, a.L, a.workspace, stride,
-                         list_off, a.ids, a.dists, a.order, a.qk, A.ldo, stream);
+    if (rc == SA_OK && a.p.rerank != 0) {
+        // the list sits at the end of the slot list, which follows the table in each region
+        const int64_t stride = (int64_t)bytes_per_slot(a.M, llog2) << glog2;
+        const int64_t list_off = ((int64_t)(compact ? 4 : 8) << glog2) + 4 * ((int64_t(1) << glog2) - 1025);
+        rc = launch_rerank(a.vec32, a.ld32, a.queries, a.ldq, a.nq, a.d, a.metric, a.k, a.L, a.workspace, stride,
+                           list_off, a.ids, a.dists, a.order, a.qk, A.ldo, stream);
+    }
+    if (rc == SA_OK && a.id_map) rc = launch_map_ids(a.ids, A.ldo, a.nq, a.k, a.order, a.qk, a.id_map, a.n, stream);
+    return rc;
 }
 
 }  // namespace sa

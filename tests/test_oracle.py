@@ -444,3 +444,33 @@ def test_rerank_on_the_search_base_keeps_the_search_result():
     ids, dists = oracle.rerank(base, q, full, 10)
     np.testing.assert_array_equal(ids, top)
     np.testing.assert_array_equal(dists, tdist)
+
+
+def test_graph_order_hand_case():
+    # 0 -> 1, 2; 1 -> 3; 2 -> 3, 1; 3 -> (none); 4 -> 0 (4 unreachable from 0); 5 isolated
+    adj = np.array([[1, 2], [3, -1], [3, 1], [-1, -1], [0, -1], [-1, -1]], np.int32)
+    # in-degrees: 0:1, 1:2, 2:1, 3:2, 4:0, 5:0 -> (1, 3) by id, then (0, 2), then (4, 5)
+    assert oracle.graph_order(adj, 0, "degree").tolist() == [1, 3, 0, 2, 4, 5]
+    # breadth-first from 0: 0, its row 1, 2; then 1's row adds 3; 2's row adds nothing; then 4, 5
+    assert oracle.graph_order(adj, 0, "bfs").tolist() == [0, 1, 2, 3, 4, 5]
+    # from 2: 2, 3, 1 (row order), then 1's row (3 seen); unreachable 0, 4, 5 by id
+    assert oracle.graph_order(adj, 2, "bfs").tolist() == [2, 3, 1, 0, 4, 5]
+    base = np.arange(12, dtype=np.float32).reshape(6, 2)
+    b2, a2, e2 = oracle.permute(base, adj, 2, [2, 3, 1, 0, 4, 5])
+    assert e2 == 0 and b2[0].tolist() == [4.0, 5.0]
+    # old row 2 = [3, 1] -> new ids [1, 2]; old row 0 (new 3) = [1, 2] -> [2, 0]
+    assert a2[0].tolist() == [1, 2] and a2[3].tolist() == [2, 0] and a2[1].tolist() == [-1, -1]
+
+
+def test_permuted_search_is_the_search_of_the_relabelled_graph():
+    # relabelling vertices and mapping result ids back gives the original search whenever
+    # no two candidates tie in distance (distinct distances: the id tie-break is unused)
+    w = synth.tiny(n=600, nq=12)
+    adj, entry, _ = oracle.build_graph(w.base, 16, 16, "knn", do_repair=False)
+    perm = oracle.graph_order(adj, entry, "bfs")
+    b2, a2, e2 = oracle.permute(w.base, adj, entry, perm)
+    i1, d1, s1 = oracle.speedann(w.base, adj, entry, w.queries, 10, 48, 4)
+    i2, d2, s2 = oracle.speedann(b2, a2, e2, w.queries, 10, 48, 4)
+    np.testing.assert_array_equal(np.where(i2 >= 0, perm[np.maximum(i2, 0)], -1), i1)
+    np.testing.assert_array_equal(d2, d1)
+    np.testing.assert_array_equal(s2["dist_comps"], s1["dist_comps"])
