@@ -591,6 +591,8 @@ def main():
     ap.add_argument("--M", type=int, default=0, help="time this walker count only (0: sweep)")
     ap.add_argument("--L", type=int, default=0, help="with --M, time this L (0: sweep)")
     ap.add_argument("--sweep-json", default="")
+    ap.add_argument("--order", choices=["none", "degree", "bfs"], default="bfs",
+                    help="vertex renumbering of the SIFT-shaped index (setup, not timed)")
     ap.add_argument("--workload", choices=["sift", "deep", "gist", "serve"], default="sift")
     ap.add_argument("--serve-M", type=int, default=1, help="walkers per served request")
     ap.add_argument("--serve-slots", type=int, default=16, help="server micro-batch slots")
@@ -642,7 +644,13 @@ def main():
     torch.cuda.synchronize()
     log(f"ground truth in {time.time() - t0:.2f}s")
 
-    ix = B.Index(base, adj, entry, metric=w.metric)
+    adj0, entry0 = adj, entry   # the original numbering, for the CPU oracle
+    perm = None
+    if args.order != "none":
+        t0 = time.time()
+        base, adj, entry, perm = B.reorder(base, adj, entry, args.order)
+        log(f"renumbered ({args.order} order) in {time.time() - t0:.1f}s")
+    ix = B.Index(base, adj, entry, metric=w.metric, id_map=perm)
     params = {}
 
     def run(M, L, stats=False, q=queries, out=None):
@@ -768,7 +776,7 @@ def main():
     E = stats[:, 2].astype(np.float64)
     bytes_launch = float((D * d * 4 + E * R * 4 + d * 4 + k * 8).sum())
     achieved = bytes_launch / (launch_ms.mean() / 1e3) / 1e9
-    workload_key = f"sift-like-{args.n}x{d}-nq{args.nq}-M{M}-L{L}"
+    workload_key = f"sift-like-{args.n}x{d}-nq{args.nq}-M{M}-L{L}-order-{args.order}"
     tr = load_traffic(workload_key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
@@ -777,7 +785,7 @@ def main():
                 "kernel_ms": round(float(launch_ms.mean()), 4)}
 
     # ---------------------------------------------------------------- CPU oracle baseline
-    cpu = None if args.no_cpu else cpu_oracle(w, adj, entry, k, L, M, args.cpu_seconds)
+    cpu = None if args.no_cpu else cpu_oracle(w, adj0, entry0, k, L, M, args.cpu_seconds)
 
     res = {
         "metric": "QPS and p50/p99 latency at recall@10=0.99, 1M×128 SIFT-shaped, 1 GPU",
@@ -796,6 +804,7 @@ def main():
             "workload": f"sift-like {args.n}x{d} (256-component mixture, sigma 20, 0..255), {args.nq} queries, k={k}",
             "graph": f"exact 64-NN, relative-neighbourhood prune to R={R}, repair (keep_local 1), medoid entry",
             "graph_build_s": round(t_graph, 1),
+            "vertex_order": args.order,
             "M": M, "L": L, "sync": "adaptive", "rho": 0.8, "staged": True,
             "recall@10": round(recall, 5), "target_reached": reached,
             "storage": "f32 vectors, int32 adjacency",
