@@ -91,3 +91,28 @@ def test_fullsize_search_sampled(full, M):
     print(f"   sampled recall@10 = {rec:.4f}", flush=True)
     assert rec >= 0.97
     assert (d[sample] >= gd).all()
+
+
+def test_fullsize_search_renumbered(full):
+    # the configuration bench.py times: the index renumbered in breadth-first order,
+    # results mapped back to original ids
+    B, w, base, adj, entry, info = full
+    base2, adj2, entry2, perm = B.reorder(base, adj, entry, "bfs")
+    p = perm.cpu().numpy()
+    assert np.array_equal(np.sort(p), np.arange(w.base.shape[0]))
+    ix = B.Index(base2, adj2, entry2, id_map=perm)
+    q = torch.from_numpy(w.queries).cuda()
+    print("case: full-size search renumbered (bfs) M=1 L=384 all 10000 queries", flush=True)
+    r = ix.search(q, 10, 384, 1, stats=True)
+    ids, d, st = r.ids.cpu().numpy(), r.dists.cpu().numpy(), r.stats.cpu().numpy()
+    assert (st[:, 5] & 3 == 0).all()
+    assert (ids >= 0).all() and (ids < w.base.shape[0]).all()
+    sample = np.random.default_rng(4).choice(w.queries.shape[0], 60, replace=False)
+    for qi in sample[:20]:
+        for j in range(10):
+            assert d[qi, j] == oracle.distance(w.queries[qi], w.base[ids[qi, j]])
+    gt, gd = oracle.knn(w.base, w.queries[sample], 10)
+    rec = oracle.recall(ids[sample], gt).mean()
+    print(f"   sampled recall@10 = {rec:.4f}", flush=True)
+    assert rec >= 0.97
+    assert (d[sample] >= gd).all()
