@@ -122,16 +122,22 @@ int sa_knn(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float 
 
 /* Two ways to compute the same exact result:
  *   SA_KNN_SCAN  double-precision accumulation on the vector units, any float data.
- *   SA_KNN_MFMA  bf16 matrix-core products, only for integer-valued data: every base and
- *                query coordinate an integer in [-255, 255], d <= 256 and k <= 128.  Then
- *                the coordinates, products and partial sums are all exact (each sum stays
- *                below 2^24 in magnitude), the squared distance |q|^2 + |x|^2 - 2 q.x is
- *                formed in 32-bit integers and rounded once to float32, and the keys equal
- *                the double-precision ones bit for bit.  It copies base and queries to a
- *                temporary bf16 array (hipMalloc, freed before returning) and checks the
- *                values on the device first.
- *   SA_KNN_AUTO  SA_KNN_MFMA when the shape allows it and the check passes, else
- *                SA_KNN_SCAN. */
+ *   SA_KNN_MFMA  bf16 matrix-core products, in one of two forms.
+ *                Integer-valued data (every base and query coordinate an integer in
+ *                [-255, 255], d <= 256, k <= 128): the coordinates, products and partial
+ *                sums are all exact (each sum stays below 2^24 in magnitude), the squared
+ *                distance |q|^2 + |x|^2 - 2 q.x is formed in 32-bit integers and rounded
+ *                once to float32, and the keys equal the double-precision ones bit for bit.
+ *                Other finite float data (d <= 128, k <= 96): coordinates split into bf16
+ *                high and low parts, three products per block give approximate distances
+ *                within a proven bound, each query keeps its k + 32 best candidates, and a
+ *                second kernel rescores them with the scan's double-precision arithmetic;
+ *                when the bound shows that no other point can enter the k best, the result
+ *                is the scan's bit for bit, and when it cannot (many distances tied
+ *                within the bound) the call runs the scan instead.  Either form copies
+ *                base and queries to temporary bf16 arrays (hipMalloc, freed before
+ *                returning) and checks the values on the device first.
+ *   SA_KNN_AUTO  SA_KNN_MFMA when a form applies and succeeds, else SA_KNN_SCAN. */
 typedef enum { SA_KNN_AUTO = 0, SA_KNN_SCAN = 1, SA_KNN_MFMA = 2 } sa_knn_path;
 
 /* sa_knn with an explicit path.  SA_KNN_MFMA on data or shapes it cannot take exactly

@@ -20,6 +20,18 @@
 // rounding does not exceed the query's current k-th distance.  Only passing products
 // build a 64-bit key and enter the query's LDS buffer, which is sorted and merged into
 // the query's top-k list as in the scan.
+//
+// Float data (d <= 128, k <= 96).  Each coordinate is split into bf16 parts x = h + l + r
+// (h = bf16(x), l = bf16(x - h), |r| <= 2^-16 |x|, 2^-14 if conversions truncated) and
+// q.x is approximated by qh.xh + qh.xl + ql.xh on the matrix cores with fp32 accumulation.
+// Its error is at most c |q| |x| with c = 3.1 2^-14 + (3d + 2) 2^-24 (the omitted terms,
+// then every fp32 rounding of the 3d products), so every approximate distance is within E_q of the exact
+// one, with E_q from |q| and the largest |x| (doubled for safety).  The candidate kernel
+// keeps the kc = k + 32 smallest approximate keys; if the kc-th approximate distance
+// exceeds the k-th by more than 2 E_q, no point outside the list can be among the k
+// nearest, and the exact kernel rescores the kc candidates with the scan's own FP64
+// arithmetic and keeps the k smallest exact keys: the scan's result, bit for bit.  If a
+// query's list cannot show that margin, the whole call falls back to the scan.
 #include "knn_select.h"
 
 #include <climits>
@@ -234,6 +246,273 @@ __global__ void __launch_bounds__(MNT) knn_mfma_kernel(MArgs A)
     }
 }
 
+// ---------------------------------------------------------------- float data
+
+constexpr int KC_EXTRA = 32;   // candidates kept beyond k
+
+struct FPrepArgs {
+    const float *x;
+    int64_t n, ld, rows;
+    int32_t d, dpad;
+    __bf16 *hi, *lo;      // rows x dpad
+    float *norm2;         // rows: |x|^2 (rounded once from double)
+    unsigned *max_norm2;  // bits of the largest |x|^2 (non-negative floats order as unsigned)
+    int32_t *bad;         // any non-finite value
+};
+
+__global__ void __launch_bounds__(256) knn_prep_float_kernel(FPrepArgs P)
+{
+    const int lane = __lane_id();
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= P.rows) return;
+    double sum = 0.0;
+    bool bad = false;
+    for (int c = lane; c < P.dpad; c += 64) {
+        float v = 0.f;
+        if (row < P.n && c < P.d) v = P.x[row * P.ld + c];
+        if (!(fabsf(v) <= 3.0e38f)) {
+            bad = true;
+            v = 0.f;
+        }
+        const __bf16 h = (__bf16)v;
+        const __bf16 l = (__bf16)(v - (float)h);
+        P.hi[row * P.dpad + c] = h;
+        P.lo[row * P.dpad + c] = l;
+        sum += (double)v * (double)v;
+    }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if (bad) atomicOr(P.bad, 1);
+    if (lane == 0) {
+        const float nf = (float)sum;
+        P.norm2[row] = row < P.n ? nf : __builtin_inff();
+        if (row < P.n) atomicMax(P.max_norm2, __float_as_uint(nf));
+    }
+}
+
+struct FArgs {
+    const __bf16 *xh, *xl;   // base parts, xrows x dpad
+    const float *xn;         // base |x|^2
+    const __bf16 *qh, *ql;   // query parts, a multiple of MQ rows x dpad
+    const float *qn;
+    int64_t n, nq, xrows;
+    int32_t dpad, kc, kpad, exclude_self;
+    int32_t *cand;           // nq x kc candidate ids (approximate order)
+    float *cand_d;           // their approximate distances
+    int32_t *cand_len;       // nq
+};
+
+// The candidate pass: as knn_mfma_kernel, with three bf16 products per block and the
+// approximate distance |q|^2 + |x|^2 - 2 q.x (or -q.x) in fp32.
+template <int KS, bool L2>
+__global__ void __launch_bounds__(MNT) knn_mfma_float_kernel(FArgs A)
+{
+    constexpr int NB = 3;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    uint64_t *top = reinterpret_cast<uint64_t *>(smem);   // [MQ][kpad]
+    uint64_t *buf = top + (size_t)MQ * A.kpad;             // [MQ][MBUF]
+    uint64_t *thr = buf + (size_t)MQ * MBUF;               // [MQ]
+    int *cnt = reinterpret_cast<int *>(thr + MQ);          // [MQ]
+    int *len = cnt + MQ;                                   // [MQ]
+    float *qns = reinterpret_cast<float *>(len + MQ);      // [MQ]
+    int *need = reinterpret_cast<int *>(qns + MQ);
+
+    const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+    const int64_t q0 = (int64_t)blockIdx.x * MQ;
+    for (int i = tid; i < MQ; i += MNT) {
+        cnt[i] = 0;
+        len[i] = 0;
+        thr[i] = q0 + i < A.nq ? KEY_EMPTY : 0ull;   // padding queries take nothing
+        qns[i] = A.qn[q0 + i];
+    }
+    if (tid == 0) *need = 0;
+
+    bf16x8 ah[4][KS], al[4][KS];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int64_t off = (q0 + rb * 16 + (lane & 15)) * A.dpad + 8 * (lane >> 4);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            ah[rb][ks] = *reinterpret_cast<const bf16x8 *>(A.qh + off + ks * 32);
+            al[rb][ks] = *reinterpret_cast<const bf16x8 *>(A.ql + off + ks * 32);
+        }
+    }
+    __syncthreads();
+
+    const int64_t ntile = A.xrows / MT;
+    bf16x8 bh[NB][KS], bl[NB][KS];
+    float bn[NB];
+#pragma unroll
+    for (int j = 0; j < NB - 1; ++j) {
+        const int64_t row = (j < ntile ? j : ntile - 1) * MT + 16 * w + (lane & 15);
+        const int64_t off = row * A.dpad + 8 * (lane >> 4);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            bh[j][ks] = *reinterpret_cast<const bf16x8 *>(A.xh + off + ks * 32);
+            bl[j][ks] = *reinterpret_cast<const bf16x8 *>(A.xl + off + ks * 32);
+        }
+        bn[j] = A.xn[row];
+    }
+
+    for (int64_t t0 = 0; t0 < ntile; t0 += NB) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int64_t t = t0 + j;
+            if (t >= ntile) break;
+            {
+                const int jn = (j + NB - 1) % NB;
+                const int64_t tn = t + NB - 1 < ntile ? t + NB - 1 : ntile - 1;
+                const int64_t row = tn * MT + 16 * w + (lane & 15);
+                const int64_t off = row * A.dpad + 8 * (lane >> 4);
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    bh[jn][ks] = *reinterpret_cast<const bf16x8 *>(A.xh + off + ks * 32);
+                    bl[jn][ks] = *reinterpret_cast<const bf16x8 *>(A.xl + off + ks * 32);
+                }
+                bn[jn] = A.xn[row];
+            }
+            f32x4 acc[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) acc[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb][ks], bh[j][ks], acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[rb][ks], bl[j][ks], acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[rb][ks], bh[j][ks], acc[rb], 0, 0, 0);
+                }
+            const int64_t col = t * MT + 16 * w + (lane & 15);
+            const float nx = bn[j];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rb * 16 + 4 * (lane >> 4) + r;
+                    if (col < A.n && !(A.exclude_self && col == q0 + row)) {
+                        const float dt = L2 ? (qns[row] + nx) - 2.f * acc[rb][r] : -acc[rb][r];
+                        const uint64_t key = make_key(dt, (int32_t)col);
+                        if (key < thr[row]) {
+                            const int pos = atomicAdd(&cnt[row], 1);
+                            buf[(size_t)row * MBUF + pos] = key;
+                            if (pos + 1 > MBUF - MT) *need = (int)(t + 1);
+                        }
+                    }
+                }
+            __syncthreads();
+            const bool last = t + 1 == ntile;
+            if (*need == (int)(t + 1) || last) {
+                for (int qr = w; qr < MQ; qr += MNT / 64) {
+                    const int c = cnt[qr];
+                    if (c == 0) continue;
+                    flush_query(top + (size_t)qr * A.kpad, &len[qr], buf + (size_t)qr * MBUF, c, A.kc);
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane == 0) {
+                        cnt[qr] = 0;
+                        if (len[qr] >= A.kc) thr[qr] = top[(size_t)qr * A.kpad + A.kc - 1];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    for (int i = tid; i < MQ * A.kc; i += MNT) {
+        const int qr = i / A.kc, j = i % A.kc;
+        const int64_t qg = q0 + qr;
+        if (qg >= A.nq) continue;
+        const bool ok = j < len[qr];
+        const uint64_t key = ok ? top[(size_t)qr * A.kpad + j] : KEY_EMPTY;
+        A.cand[qg * A.kc + j] = ok ? key_id(key) : -1;
+        A.cand_d[qg * A.kc + j] = ok ? key_dist(key) : __builtin_inff();
+        if (j == 0) A.cand_len[qg] = len[qr];
+    }
+}
+
+struct EArgs {
+    const float *base;
+    int64_t n, ld;
+    const float *queries;
+    int64_t nq, ldq;
+    int32_t d, k, kc, metric;
+    const int32_t *cand;
+    const float *cand_d;
+    const int32_t *cand_len;
+    const float *qn;            // |q|^2 per query (the candidate pass's)
+    const unsigned *max_norm2;
+    int32_t *ids;
+    float *dists;
+    int32_t *failed;            // queries whose list could not show the margin
+};
+
+// One wavefront per query: the margin test, then the exact keys of the candidates with
+// the scan's arithmetic (double, index order, separately rounded multiply and add, one
+// rounding to float) and the k smallest.
+__global__ void __launch_bounds__(64) knn_exact_kernel(EArgs E)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    float *qs = reinterpret_cast<float *>(smem);
+    const int lane = __lane_id();
+    const int64_t q = blockIdx.x;
+    const int nc = E.cand_len[q];
+    const int32_t *cd = E.cand + q * E.kc;
+    if (nc >= E.kc) {
+        // (2^-14 rather than 2^-16: the bound holds even for truncating bf16 conversions)
+        const double c = 3.1 / 16384.0 + (3.0 * E.d + 2.0) / 16777216.0;
+        const double nq_ = sqrt((double)E.qn[q]), nm = sqrt((double)__uint_as_float(*E.max_norm2));
+        const double err = E.metric == SA_L2 ? 2.0 * (2.0 * c * nq_ * nm + 4.0 / 16777216.0 * (nq_ + nm) * (nq_ + nm))
+                                             : 2.0 * (c * nq_ * nm + 2.0 / 16777216.0 * nq_ * nm);
+        const double dk = E.cand_d[q * E.kc + E.k - 1], dl = E.cand_d[q * E.kc + E.kc - 1];
+        if (!(dl > dk + 2.0 * err)) {
+            if (lane == 0) atomicAdd(E.failed, 1);
+            return;
+        }
+    }
+    for (int c = lane; c < E.d; c += 64) qs[c] = E.queries[q * E.ldq + c];
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long key[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int j = lane + 64 * h;
+        key[h] = KEY_EMPTY;
+        if (j < nc && j < E.kc) {
+            const int32_t id = cd[j];
+            const float *x = E.base + (int64_t)id * E.ld;
+            double acc = 0.0;
+            if (E.metric == SA_L2) {
+                for (int c = 0; c < E.d; ++c) {
+                    const double t = (double)qs[c] - (double)x[c];
+                    acc += t * t;
+                }
+            } else {
+                for (int c = 0; c < E.d; ++c) acc += (double)qs[c] * (double)x[c];
+            }
+            key[h] = make_key(E.metric == SA_L2 ? (float)acc : (float)(-acc), id);
+        }
+    }
+    knn_detail::sort128(key[0], key[1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int j = lane + 64 * h;
+        if (j < E.k) {
+            const bool ok = key[h] != KEY_EMPTY;
+            E.ids[q * E.k + j] = ok ? key_id(key[h]) : -1;
+            E.dists[q * E.k + j] = ok ? key_dist(key[h]) : __builtin_inff();
+        }
+    }
+}
+
+using FKernel = void (*)(FArgs);
+
+FKernel pick_float_kernel(int ks, int metric)
+{
+    switch (ks) {
+    case 1: return metric == SA_L2 ? knn_mfma_float_kernel<1, true> : knn_mfma_float_kernel<1, false>;
+    case 2: return metric == SA_L2 ? knn_mfma_float_kernel<2, true> : knn_mfma_float_kernel<2, false>;
+    case 3: return metric == SA_L2 ? knn_mfma_float_kernel<3, true> : knn_mfma_float_kernel<3, false>;
+    case 4: return metric == SA_L2 ? knn_mfma_float_kernel<4, true> : knn_mfma_float_kernel<4, false>;
+    default: return nullptr;
+    }
+}
+
 using MKernel = void (*)(MArgs);
 
 template <int KS>
@@ -326,6 +605,73 @@ int launch_knn_mfma(const float *base, int64_t n, int32_t d, int64_t ld, const f
     return SA_OK;
 }
 
+// The float path for d <= 128 and k <= 96; *ran is false when it cannot show every
+// query's margin (the caller then runs the scan).  Synchronous.
+int launch_knn_mfma_float(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq,
+                          int64_t ldq, int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists,
+                          bool *ran, hipStream_t s)
+{
+    *ran = false;
+    const int ks = (d + 31) / 32;
+    const int dpad = 32 * ks;
+    const int kc = k + KC_EXTRA;
+    const int64_t xrows = (n + MT - 1) / MT * MT;
+    const bool shared_q = queries == base && ldq == ld && nq <= n;
+    const int64_t qrows = shared_q ? xrows : (nq + MQ - 1) / MQ * MQ;
+    const size_t xp = align256((size_t)xrows * dpad * 2), xn_b = align256((size_t)xrows * 4);
+    const size_t qp = shared_q ? 0 : align256((size_t)qrows * dpad * 2), qn_b = shared_q ? 0 : align256((size_t)qrows * 4);
+    const size_t cand_b = align256((size_t)nq * kc * 4), len_b = align256((size_t)nq * 4);
+    DeviceBlock mem;
+    const size_t total = 2 * xp + xn_b + 2 * qp + qn_b + 2 * cand_b + len_b + 256;
+    if (hipMalloc(&mem.p, total) != hipSuccess) {
+        (void)hipGetLastError();
+        mem.p = nullptr;
+        return set_error(SA_ENOMEM, "hipMalloc of the bf16 parts failed");
+    }
+    unsigned char *m = static_cast<unsigned char *>(mem.p);
+    __bf16 *xh = reinterpret_cast<__bf16 *>(m); m += xp;
+    __bf16 *xl = reinterpret_cast<__bf16 *>(m); m += xp;
+    float *xn = reinterpret_cast<float *>(m); m += xn_b;
+    __bf16 *qh = shared_q ? xh : reinterpret_cast<__bf16 *>(m); m += qp;
+    __bf16 *ql = shared_q ? xl : reinterpret_cast<__bf16 *>(m); m += qp;
+    float *qn = shared_q ? xn : reinterpret_cast<float *>(m); m += qn_b;
+    int32_t *cand = reinterpret_cast<int32_t *>(m); m += cand_b;
+    float *cand_d = reinterpret_cast<float *>(m); m += cand_b;
+    int32_t *cand_len = reinterpret_cast<int32_t *>(m); m += len_b;
+    unsigned *flags = reinterpret_cast<unsigned *>(m);   // [0] max |x|^2, [1] bad, [2] failed, [3] unused norm
+    SA_HIP(hipMemsetAsync(flags, 0, 16, s));
+    FPrepArgs P{base, n, ld, xrows, d, dpad, xh, xl, xn, flags, reinterpret_cast<int32_t *>(flags + 1)};
+    hipLaunchKernelGGL(knn_prep_float_kernel, dim3((unsigned)((xrows + 3) / 4)), dim3(256), 0, s, P);
+    SA_HIP(hipGetLastError());
+    if (!shared_q) {
+        // queries do not take part in the largest |x|: their maximum goes to an unused word
+        FPrepArgs Q{queries, nq, ldq, qrows, d, dpad, qh, ql, qn, flags + 3, reinterpret_cast<int32_t *>(flags + 1)};
+        hipLaunchKernelGGL(knn_prep_float_kernel, dim3((unsigned)((qrows + 3) / 4)), dim3(256), 0, s, Q);
+        SA_HIP(hipGetLastError());
+    }
+    FArgs A;
+    A.xh = xh; A.xl = xl; A.xn = xn; A.qh = qh; A.ql = ql; A.qn = qn;
+    A.n = n; A.nq = nq; A.xrows = xrows;
+    A.dpad = dpad; A.kc = kc; A.kpad = (kc + 63) / 64 * 64; A.exclude_self = exclude_self;
+    A.cand = cand; A.cand_d = cand_d; A.cand_len = cand_len;
+    const size_t lds = 8ull * MQ * A.kpad + 8ull * MQ * MBUF + 8ull * MQ + 3ull * 4 * MQ + 16;
+    FKernel kern = pick_float_kernel(ks, metric);
+    if (!kern || lds > 160u * 1024u) return SA_OK;
+    SA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+    hipLaunchKernelGGL(kern, dim3((unsigned)((nq + MQ - 1) / MQ)), dim3(MNT), lds, s, A);
+    SA_HIP(hipGetLastError());
+    EArgs E{base, n, ld, queries, nq, ldq, d, k, kc, metric, cand, cand_d, cand_len, qn, flags, ids, dists,
+            reinterpret_cast<int32_t *>(flags + 2)};
+    hipLaunchKernelGGL(knn_exact_kernel, dim3((unsigned)nq), dim3(64), 4 * (size_t)dpad, s, E);
+    SA_HIP(hipGetLastError());
+    unsigned hf[3] = {0, 0, 0};
+    SA_HIP(hipMemcpyAsync(hf, flags, 12, hipMemcpyDeviceToHost, s));
+    SA_HIP(hipStreamSynchronize(s));
+    *ran = hf[1] == 0 && hf[2] == 0;
+    return SA_OK;
+}
+
 }  // namespace
 
 int launch_knn(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq, int64_t ldq,
@@ -349,8 +695,19 @@ int launch_knn(const float *base, int64_t n, int32_t d, int64_t ld, const float 
             if (path_used) *path_used = SA_KNN_MFMA;
             return SA_OK;
         }
+        // not integer data: the float path, where its shape allows
+        if (d <= 128 && k <= 96 && n >= 1) {
+            const int rf = launch_knn_mfma_float(base, n, d, ld, queries, nq, ldq, k, metric, exclude_self, ids,
+                                                 dists, &ran, stream);
+            if (rf != SA_OK) return rf;
+            if (ran) {
+                if (path_used) *path_used = SA_KNN_MFMA;
+                return SA_OK;
+            }
+        }
         if (path == SA_KNN_MFMA)
-            return set_error(SA_EUNSUPPORTED, "the MFMA kNN path needs every coordinate to be an integer in [-255, 255]");
+            return set_error(SA_EUNSUPPORTED, "the MFMA kNN path needs integer coordinates in [-255, 255] (d <= 256, "
+                             "k <= 128) or finite floats with d <= 128 and k <= 96 whose candidates separate");
     }
     const int rc = launch_knn_scan(base, n, d, ld, queries, nq, ldq, k, metric, exclude_self, ids, dists, stream);
     if (rc != SA_OK) return rc;

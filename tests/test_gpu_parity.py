@@ -146,16 +146,27 @@ def test_knn_paths_agree_sift(B):
 
 
 def test_knn_path_selection(B):
-    w = synth.tiny()  # float data: the scan
+    # float data with d <= 128 and k <= 96 runs on the matrix cores (bf16 hi/lo products
+    # rescored in double); the result is the oracle's whichever path runs
+    w = synth.tiny()
     print("case: knn path selection", flush=True)
     ids, dd, used = B.knn(dev(w.base), dev(w.queries), 10, return_path=True)
-    assert used == "scan"
-    with pytest.raises(B.SpeedAnnError, match="integer"):
-        B.knn(dev(w.base), dev(w.queries), 10, path="mfma")
+    assert used == "mfma"
+    eids, ed = oracle.knn(w.base, w.queries, 10)
+    np.testing.assert_array_equal(host(ids), eids)
+    np.testing.assert_array_equal(host(dd), ed)
     g = synth.integer_grid(700, 16, 9, config=93)
-    for base, q, k, why in ((g.base * 0.5, g.queries, 10, "integer"),       # half-integers
-                            (g.base + 250.0, g.queries, 10, "integer"),     # beyond 255
-                            (g.base, g.queries, 129, "k <= 128")):
+    wide = synth.tiny(n=600, nq=5, d=200)
+    # half-integers and integers beyond 255 leave the integer path; their many exact ties
+    # may keep the float path from separating its candidates, and then the scan runs
+    for base, q, k in ((g.base * 0.5, g.queries, 10), (g.base + 250.0, g.queries, 10)):
+        ids, dd, used = B.knn(dev(base), dev(q), k, return_path=True)
+        assert used in ("mfma", "scan")
+        eids, ed = oracle.knn(base, q, k)
+        np.testing.assert_array_equal(host(ids), eids)
+        np.testing.assert_array_equal(host(dd), ed)
+    # beyond both matrix-core paths: d > 128 with float data, k > 128
+    for base, q, k, why in ((wide.base, wide.queries, 10, "d <= 128"), (g.base, g.queries, 129, "k <= 128")):
         ids, dd, used = B.knn(dev(base), dev(q), k, return_path=True)
         assert used == "scan"
         eids, ed = oracle.knn(base, q, k)
@@ -163,11 +174,6 @@ def test_knn_path_selection(B):
         np.testing.assert_array_equal(host(dd), ed)
         with pytest.raises(B.SpeedAnnError, match=why):
             B.knn(dev(base), dev(q), k, path="mfma")
-    wide = synth.integer_grid(300, 260, 4, config=94)
-    ids, dd, used = B.knn(dev(wide.base), dev(wide.queries), 10, return_path=True)
-    assert used == "scan"
-    with pytest.raises(B.SpeedAnnError, match="d <= 256"):
-        B.knn(dev(wide.base), dev(wide.queries), 10, path="mfma")
 
 
 # ------------------------------------------------------------------ graph construction
@@ -383,3 +389,30 @@ def test_workspace_stays_zero_and_reusable(B, sift_setup):
         eids, ed, est = oracle.speedann(w.base, adj, entry, w.queries, 10, L, M)
         np.testing.assert_array_equal(host(r.ids), eids)
         np.testing.assert_array_equal(host(r.stats)[:, 3], est["dist_comps"])
+
+
+@pytest.mark.parametrize("case", ["deep-ip", "uniform-l2", "deep-self-l2", "k96", "k1"])
+def test_knn_float_mfma_equals_scan(B, case):
+    # float data on the matrix cores: candidates from bf16 hi/lo products, rescored in
+    # double; the result must be the scan's bit for bit, and the path must be the MFMA one
+    if case == "uniform-l2":
+        w = synth.tiny(n=7000, nq=90)
+        base, q, metric, k, excl = w.base, w.queries, "l2", 16, False
+    else:
+        w = synth.deep_like(n=9000, nq=70)
+        base, q = w.base, w.queries
+        metric = "ip" if case == "deep-ip" else "l2"
+        k = {"k96": 96, "k1": 1}.get(case, 64)
+        excl = case == "deep-self-l2"
+        if excl:
+            q = None
+    print(f"case: knn float mfma vs scan {case}", flush=True)
+    qd = None if q is None else dev(q)
+    ids, d, path = B.knn(dev(base), qd, k, metric=metric, exclude_self=excl, path="auto", return_path=True)
+    sids, sd = B.knn(dev(base), qd, k, metric=metric, exclude_self=excl, path="scan")
+    assert path == "mfma"
+    np.testing.assert_array_equal(host(ids), host(sids))
+    np.testing.assert_array_equal(host(d), host(sd))
+    if case == "k1":
+        eids, ed = oracle.knn(base, q, k, metric=metric)
+        np.testing.assert_array_equal(host(ids), eids)
