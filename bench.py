@@ -27,9 +27,9 @@ final list, resident on the GPU behind the serving loop.  Recall targets {0.9, 0
 0.999} are mapped to L on a calibration sample; each request draws a target; Poisson
 arrival traces at 10k-500k queries/s are replayed natively and p50 / p99 latency
 (completion minus scheduled arrival) and achieved throughput are reported per rate.
-The 10M graph's candidates come from overlapping partitions (each point's two nearest
-of 2048 sampled centroids, exact kNN inside each partition): an approximate kNN graph
-instead of the exact one, which at 10M would take the FP64 scan about 40 minutes.
+The 10M graph is built from exact 64-NN candidates computed on the matrix cores in
+1M-row chunks (--serve-graph partition: from overlapping partitions instead, each
+point's two nearest of 2048 sampled centroids with exact kNN inside each partition).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -47,9 +47,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # the served workload runs up to 16 micro-batches at once: give each its own hardware
-# queue (HIP's default is 4); read before the runtime starts, so set it here
+# queue (HIP's default is 4; streams beyond the queue count share queues and serialise
+# their kernels).  Read when the runtime starts, so set here, over any inherited value.
 if "--workload" in sys.argv and "serve" in sys.argv:
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 L_SWEEP = [32, 48, 64, 96, 128, 192, 256, 384, 512]
 M_SWEEP = [1, 2, 4, 8, 16]
@@ -255,7 +256,7 @@ def deep_main(args, torch, B, synth, dev):
     print(json.dumps(res), flush=True)
 
 
-def build_graph_logged(torch, B, base, knn_k, R, prune_mode, chunk=100_000):
+def build_graph_logged(torch, B, base, knn_k, R, prune_mode, chunk=100_000, metric="l2"):
     """The steps of sa_build_graph (medoid entry, exact knn_k-NN candidates, pruning,
     reverse edges, repair), with the candidate search cut into row chunks so that each
     finished chunk is logged.  A chunk's rows search the whole base with k = knn_k + 1
@@ -266,7 +267,7 @@ def build_graph_logged(torch, B, base, knn_k, R, prune_mode, chunk=100_000):
     t0 = time.time()
     for s0 in range(0, n, chunk):
         e0 = min(n, s0 + chunk)
-        ids, _ = B.knn(base, base[s0:e0], knn_k + 1)
+        ids, _ = B.knn(base, base[s0:e0], knn_k + 1, metric=metric)
         own = torch.arange(s0, e0, device=base.device, dtype=torch.int32)[:, None]
         keep = ids != own
         # rows where the own id is not among the knn_k + 1 keep their first knn_k
@@ -274,9 +275,9 @@ def build_graph_logged(torch, B, base, knn_k, R, prune_mode, chunk=100_000):
         cand[s0:e0] = ids[keep & first].view(e0 - s0, knn_k)
         torch.cuda.synchronize()
         log(f"candidates: rows {e0:,} of {n:,} in {time.time() - t0:.1f}s")
-    adj = B.prune(base, cand, R, prune_mode)
-    B.reverse_edges(base, adj)
-    bridges, comps = B.repair(base, adj, entry, keep_local=1)
+    adj = B.prune(base, cand, R, prune_mode, metric=metric)
+    B.reverse_edges(base, adj, metric=metric)
+    bridges, comps = B.repair(base, adj, entry, keep_local=1, metric=metric)
     torch.cuda.synchronize()
     return adj, entry, {"bridges": bridges, "components": comps}
 
@@ -359,7 +360,11 @@ def serve_main(args, torch, B, synth, dev):
     queries = torch.from_numpy(w.queries).to(dev)
     d, R, k, Ms = w.base.shape[1], w.graph_R, 10, args.serve_M
     t0 = time.time()
-    adj, entry, ginfo = build_graph_partitioned(torch, B, base, w.graph_knn, R, w.graph_prune, w.metric)
+    if args.serve_graph == "exact":
+        adj, entry, ginfo = build_graph_logged(torch, B, base, w.graph_knn, R, w.graph_prune, chunk=1_000_000,
+                                               metric=w.metric)
+    else:
+        adj, entry, ginfo = build_graph_partitioned(torch, B, base, w.graph_knn, R, w.graph_prune, w.metric)
     t_graph = time.time() - t0
     log(f"graph built in {t_graph:.1f}s: entry {entry}, {ginfo}")
     t0 = time.time()
@@ -442,8 +447,9 @@ def serve_main(args, torch, B, synth, dev):
         "config": {
             "workload": f"deep-like {args.n}x{d} (1024-component mixture, sigma 1, coordinate variance 1/i, unit "
                         f"norm), inner product, {args.nq} distinct queries cycled, k={k}",
-            "graph": f"approximate 64-NN candidates from 2048 overlapping partitions, relative-neighbourhood prune "
-                     f"to R={R}, reverse edges, repair, medoid entry",
+            "graph": (f"exact 64-NN (matrix cores, 1M-row chunks)" if args.serve_graph == "exact" else
+                      "approximate 64-NN candidates from 2048 overlapping partitions") +
+                     f", relative-neighbourhood prune to R={R}, reverse edges, repair, medoid entry",
             "graph_build_s": round(t_graph, 1), "M": Ms, "rerank": "whole list", "calibration": sweep,
             "target_to_L": {str(t): L for t, L in tL.items()},
             "server": {"slots": args.serve_slots, "max_batch": 1024, "workspace_bytes": 8 << 30,
@@ -596,6 +602,8 @@ def main():
     ap.add_argument("--workload", choices=["sift", "deep", "gist", "serve"], default="sift")
     ap.add_argument("--serve-M", type=int, default=1, help="walkers per served request")
     ap.add_argument("--serve-slots", type=int, default=16, help="server micro-batch slots")
+    ap.add_argument("--serve-graph", choices=["exact", "partition"], default="exact",
+                    help="10M graph candidates: exact kNN (matrix cores, row chunks) or overlapping partitions")
     ap.add_argument("--rates", default="10000,50000,100000,200000,500000", help="Poisson arrival rates to replay")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run a plain elementwise copy of this many MiB (read and written "
