@@ -52,7 +52,7 @@ sys.path.insert(0, ROOT)
 if "--workload" in sys.argv and "serve" in sys.argv:
     os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
-L_SWEEP = [32, 48, 64, 96, 128, 192, 256, 384, 512]
+L_SWEEP = [32, 48, 64, 96, 128, 160, 192, 224, 256, 288, 320, 352, 384, 448, 512]
 M_SWEEP = [1, 2, 4, 8, 16]
 TARGET = 0.99
 HBM_PEAK_GBS = 8000.0
