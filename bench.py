@@ -46,10 +46,10 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-# the served workload runs up to 16 micro-batches at once: give each its own hardware
-# queue (HIP's default is 4; streams beyond the queue count share queues and serialise
+# the served workload runs up to 16 micro-batches at once, the batched one up to 8
+# streams: give each its own hardware queue (HIP's default is 4; streams beyond the queue count share queues and serialise
 # their kernels).  Read when the runtime starts, so set here, over any inherited value.
-if "--workload" in sys.argv and "serve" in sys.argv:
+if "--workload" in sys.argv and ("serve" in sys.argv or "gist" in sys.argv):
     os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 L_SWEEP = [32, 48, 64, 96, 128, 160, 192, 224, 256, 288, 320, 352, 384, 448, 512]

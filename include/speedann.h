@@ -287,7 +287,8 @@ int sa_index_set_id_map(sa_index *index, const int32_t *id_map_dev);
  *
  * The plan groups the queries into classes of equal M and equal register-queue size
  * (ceil(L / 64) rounded up to 1, 2, 4, 6, 8 or 16), one kernel launch each, longest L
- * first within a class; classes go to up to four internal streams.  sa_batch_run only
+ * first within a class; classes go to up to eight internal streams (each wants a
+ * hardware queue of its own: GPU_MAX_HW_QUEUES, default 4).  sa_batch_run only
  * enqueues kernel launches and event records and waits, so it can be captured in a HIP
  * graph from hip_stream (the classes become parallel branches) and replayed.  The
  * workspace holds the uploaded per-query arrays and one visited-set region per query
@@ -316,14 +317,14 @@ int sa_batch_upload(const sa_batch *batch, void *workspace, size_t ws_bytes, voi
 int sa_batch_run(const sa_batch *batch, const float *queries_dev, int64_t ldq, int32_t *ids_dev, float *dists_dev,
                  int64_t ldo, sa_query_stats *stats_dev, void *workspace, size_t ws_bytes, void *hip_stream);
 
-/* Autotuner: times sa_batch_run (best of reps after one warm run) for 1, 2 and 4
+/* Autotuner: times sa_batch_run (best of reps after one warm run) for 1, 2, 4 and 8
  * streams and, when a class has two or more walkers and params left lds_hash_slots at
  * 0, with and without LDS visited tables for those classes; keeps the fastest.  Results
  * do not depend on the choice.  Synchronous; overwrites ids_dev and dists_dev. */
 int sa_batch_tune(sa_batch *batch, const float *queries_dev, int64_t ldq, int32_t *ids_dev, float *dists_dev,
                   int64_t ldo, void *workspace, size_t ws_bytes, int32_t reps, void *hip_stream);
 
-/* Sets the configuration by hand: streams 1, 2 or 4; lds_hash_slots for the classes with
+/* Sets the configuration by hand: streams 1, 2, 4 or 8; lds_hash_slots for the classes with
  * two or more walkers (as in sa_search_params). */
 int sa_batch_set_config(sa_batch *batch, int32_t streams, int32_t lds_hash_slots);
 

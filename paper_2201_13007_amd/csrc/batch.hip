@@ -7,11 +7,11 @@
 // launch with one workgroup per query; it takes its queries longest L first, so the
 // hardware dispatcher, which hands out workgroups in index order as slots free up, runs
 // the long searches first and the short ones fill the tail.  Classes are spread over up
-// to four streams, longest class first onto the least loaded stream; a run forks them
+// to eight streams, longest class first onto the least loaded stream; a run forks them
 // from the caller's stream and joins them back with events, so a graph captured from
 // that stream holds every class as a parallel branch.  The autotuner times the choices
-// that leave every result unchanged: the number of streams and, for classes with two or
-// more walkers, whether the visited set starts in an LDS table.
+// that leave every result unchanged: the number of streams (1, 2, 4, 8) and, for classes
+// with two or more walkers, whether the visited set starts in an LDS table.
 #include "sa_internal.h"
 
 #include <algorithm>
@@ -22,7 +22,7 @@
 namespace sa {
 namespace {
 
-constexpr int MAX_STREAMS = 4;
+constexpr int MAX_STREAMS = 8;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -284,7 +284,7 @@ int sa_batch_tune(sa_batch *b, const float *queries_dev, int64_t ldq, int32_t *i
     std::string js = "{\"candidates\":[";
     bool first = true;
     for (int32_t lds : lds_modes) {
-        for (int ns : {1, 2, 4}) {
+        for (int ns : {1, 2, 4, 8}) {
             if (ns > 1 && (int)b->cls.size() < 2) continue;
             for (BatchClass &c : b->cls)
                 if (c.M >= 2) c.lds = lds;
@@ -332,7 +332,8 @@ int sa_batch_tune(sa_batch *b, const float *queries_dev, int64_t ldq, int32_t *i
 int sa_batch_set_config(sa_batch *b, int32_t streams, int32_t lds_hash_slots)
 {
     if (!b) return set_error(SA_EINVAL, "batch is NULL");
-    if (streams != 1 && streams != 2 && streams != 4) return set_error(SA_EINVAL, "streams must be 1, 2 or 4");
+    if (streams != 1 && streams != 2 && streams != 4 && streams != 8)
+        return set_error(SA_EINVAL, "streams must be 1, 2, 4 or 8");
     for (BatchClass &c : b->cls)
         if (c.M >= 2) c.lds = lds_hash_slots;
     assign_streams(b, streams);

@@ -72,7 +72,7 @@ def test_batch_equals_search_under_every_config(B, gist):
         want_ids[i, :k[i]] = host(r.ids)[0]
         want_d[i, :k[i]] = host(r.dists)[0]
     bt = B.Batch(ix, L, k, M, rho=0.8)
-    for streams in (1, 2, 4):
+    for streams in (1, 2, 4, 8):
         for lds in (0, -1, 4096):
             print(f"case: batch config streams={streams} lds_hash_slots={lds}", flush=True)
             bt.set_config(streams, lds)
@@ -81,7 +81,7 @@ def test_batch_equals_search_under_every_config(B, gist):
             np.testing.assert_array_equal(host(r.dists), want_d)
     print("case: batch tune", flush=True)
     t = bt.tune(q, reps=1)
-    assert len(t["candidates"]) >= 3 and t["chosen"]["streams"] in (1, 2, 4)
+    assert len(t["candidates"]) >= 4 and t["chosen"]["streams"] in (1, 2, 4, 8)
     r = bt.run(q)
     np.testing.assert_array_equal(host(r.ids), want_ids)
     d = bt.describe()

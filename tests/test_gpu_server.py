@@ -138,3 +138,21 @@ def test_server_rerank_bf16(B, deep):
         np.testing.assert_array_equal(ids[i, :k[i]], want[i][0], err_msg=f"request {i}")
         np.testing.assert_array_equal(dists[i, :k[i]], want[i][1], err_msg=f"request {i}")
     srv.close()
+
+
+def test_server_renumbered_index(B, deep):
+    # a renumbered index behind the server returns original ids, equal to its own searches
+    w, adj, entry, k, L, M = deep
+    base2, adj2, entry2, perm = B.reorder(dev(w.base), dev(adj), entry, "bfs")
+    ix = B.Index(base2, adj2, entry2, metric="ip", id_map=perm)
+    q = dev(w.queries)
+    n = 48
+    want = [host(ix.search(q[i:i + 1], int(k[i]), int(L[i]), int(M[i])).ids)[0] for i in range(n)]
+    print("case: server over a renumbered index, 48 requests", flush=True)
+    srv = B.Server(ix, slots=4, max_batch=8, k_max=20)
+    ids, dists, lat, wall = srv.replay(w.queries[:n], k[:n], L[:n], M[:n], (np.arange(n) * 20_000).astype(np.int64))
+    for i in range(n):
+        np.testing.assert_array_equal(ids[i, :k[i]], want[i], err_msg=f"request {i}")
+    # original numbering: the distances are those of the original rows
+    np.testing.assert_allclose(dists[:n, 0], -(w.base[ids[:n, 0]] * w.queries[:n]).sum(1), rtol=1e-5, atol=1e-6)
+    srv.close()
