@@ -111,9 +111,26 @@ def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors"):
         t_cpu += time.perf_counter() - s0
         done += n1
         bs = min(bs * 2, 2048)
+    # one query at a time on one thread: the paper's latency measure, as percentiles
+    lat = []
+    for i in range(min(100, nq)):
+        s0 = time.perf_counter()
+        oracle.speedann(w.base, adj_h, entry, w.queries[i:i + 1], k, L, M, sync="adaptive", rho=0.8, staged=True,
+                        metric=w.metric)
+        lat.append((time.perf_counter() - s0) * 1e3)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     cpu = {"value": round(done / t_cpu, 1), "unit": "queries/s", "cores": nthreads, "kind": "oracle",
            "sample": f"first {done} of the {nq} queries, same graph, {storage}, M={M}, L={L}, adaptive rho 0.8 "
-                     f"staged, lockstep emulation of Algorithm 3 in plain C, one query per OpenMP thread"}
+                     f"staged, lockstep emulation of Algorithm 3 in plain C, one query per OpenMP thread",
+           "cpu_model": model,
+           "latency_p50_ms": round(float(np.percentile(lat, 50)), 4),
+           "latency_p99_ms": round(float(np.percentile(lat, 99)), 4),
+           "latency_sample": f"first {len(lat)} queries one at a time, one thread, host wall time"}
     log(f"cpu oracle: {cpu['value']} q/s on {nthreads} threads ({done} queries, {t_cpu:.1f}s)")
     return cpu
 
@@ -786,11 +803,15 @@ def main():
     achieved = bytes_launch / (launch_ms.mean() / 1e3) / 1e9
     workload_key = f"sift-like-{args.n}x{d}-nq{args.nq}-M{M}-L{L}-order-{args.order}"
     tr = load_traffic(workload_key)
+    gc = B.gather_ceiling(base)
+    log(f"gather ceiling: {gc['GBs']:.0f} GB/s for random {gc['row_bytes']}-byte rows")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": tr["bytes_per_launch"] if tr else None,
                 "algorithmic_bytes_per_launch": round(bytes_launch),
-                "kernel_ms": round(float(launch_ms.mean()), 4)}
+                "kernel_ms": round(float(launch_ms.mean()), 4),
+                "gather_ceiling_GBs": round(gc["GBs"], 1),
+                "frac_of_gather_ceiling": round(achieved / gc["GBs"], 4)}
 
     # ---------------------------------------------------------------- CPU oracle baseline
     cpu = None if args.no_cpu else cpu_oracle(w, adj0, entry0, k, L, M, args.cpu_seconds)

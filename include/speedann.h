@@ -277,6 +277,18 @@ int sa_permute_graph(const int32_t *adj_dev, int64_t n, int32_t R, const int32_t
  * stream. */
 int sa_index_set_id_map(sa_index *index, const int32_t *id_map_dev);
 
+/* ------------------------------------------------------------------ measurement
+ *
+ * Gather ceiling (a measurement tool, not part of the search): `waves` wavefronts each
+ * read iters x 64 / g whole rows of vec_dev (n rows of d float32, stride ld) chosen by
+ * a 32-bit hash of (seed, wavefront, pass, group), g lanes per row as the search's
+ * distance step uses them, and write one float per lane to sink_dev (waves x 64
+ * floats).  Rows read = waves * iters * 64 / g, g = the search's lanes per vector for
+ * d (for d = 128: 8).  iters and waves are positive multiples of 4; n < 2^32.
+ * Enqueued on hip_stream; time it with events. */
+int sa_gather_probe(const float *vec_dev, int64_t n, int32_t d, int64_t ld, int64_t iters, int32_t waves,
+                    uint32_t seed, float *sink_dev, void *hip_stream);
+
 /* ------------------------------------------------------------------ batches
  *
  * A batch is a fixed set of nq queries, each with its own L, k and M, searched together:

@@ -24,7 +24,8 @@ EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_quan
            "sa_batch_create", "sa_batch_destroy", "sa_batch_workspace_bytes", "sa_batch_upload", "sa_batch_run",
            "sa_batch_tune", "sa_batch_set_config", "sa_batch_describe", "sa_server_default_config",
            "sa_server_create", "sa_server_destroy", "sa_server_submit", "sa_server_poll", "sa_server_replay",
-           "sa_server_stats", "sa_graph_order", "sa_permute_rows", "sa_permute_graph", "sa_index_set_id_map"]
+           "sa_server_stats", "sa_graph_order", "sa_permute_rows", "sa_permute_graph", "sa_index_set_id_map",
+           "sa_gather_probe"]
 
 
 class SearchParams(C.Structure):
@@ -102,11 +103,12 @@ def lib():
         L.sa_permute_rows.argtypes = [vp, i64, i64, vp, vp, vp]
         L.sa_permute_graph.argtypes = [vp, i64, i32, vp, vp, vp, vp]
         L.sa_index_set_id_map.argtypes = [vp, vp]
+        L.sa_gather_probe.argtypes = [vp, i64, i32, i64, i64, i32, C.c_uint32, vp, vp]
         for name in ("sa_knn", "sa_knn_ex", "sa_quantize", "sa_index_create_q", "sa_medoid", "sa_prune", "sa_reverse_edges", "sa_repair", "sa_build_graph", "sa_index_create",
                      "sa_search", "sa_batch_create", "sa_batch_upload", "sa_batch_run", "sa_batch_tune",
                      "sa_batch_set_config", "sa_server_create", "sa_server_submit", "sa_server_replay",
                      "sa_server_stats", "sa_graph_order", "sa_permute_rows", "sa_permute_graph",
-                     "sa_index_set_id_map"):
+                     "sa_index_set_id_map", "sa_gather_probe"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -548,3 +550,27 @@ def reorder(base: torch.Tensor, adj: torch.Tensor, entry: int, mode="bfs"):
     adj2, inv = permute_graph(adj, perm)
     torch.cuda.synchronize()
     return base2, adj2, int(inv[entry].item()), perm
+
+
+def gather_ceiling(vec: torch.Tensor, iters=64, waves=8192, reps=5, seed=1) -> dict:
+    """Random whole-row gather bandwidth over vec (sa_gather_probe), best-of-reps median."""
+    vec = pad_dim(_mat(vec, "vectors"))
+    n, d = vec.shape
+    lpv = 1
+    while lpv < 64 and 4 * lpv < d // 4:
+        lpv *= 2
+    sink = torch.empty(waves * 64, dtype=torch.float32, device=vec.device)
+    s = torch.cuda.current_stream()
+    ms = []
+    for r in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        _check(lib().sa_gather_probe(vec.data_ptr(), n, d, vec.stride(0), int(iters), int(waves), int(seed + r),
+                                     sink.data_ptr(), int(s.cuda_stream)), "sa_gather_probe")
+        b.record()
+        torch.cuda.synchronize()
+        if r:
+            ms.append(a.elapsed_time(b))
+    rows = waves * iters * (64 // lpv)
+    t = sorted(ms)[len(ms) // 2]
+    return {"GBs": rows * d * 4 / (t / 1e3) / 1e9, "rows": rows, "row_bytes": d * 4, "ms": t}

@@ -416,3 +416,14 @@ def test_knn_float_mfma_equals_scan(B, case):
     if case == "k1":
         eids, ed = oracle.knn(base, q, k, metric=metric)
         np.testing.assert_array_equal(host(ids), eids)
+
+
+def test_gather_probe(B):
+    w = synth.sift_like(n=20_000, nq=1)
+    print("case: gather probe 20000x128", flush=True)
+    g = B.gather_ceiling(dev(w.base), iters=8, waves=64, reps=1)
+    assert g["GBs"] > 0 and g["rows"] == 64 * 8 * 8 and g["row_bytes"] == 512
+    sink = torch.empty(64 * 64, dtype=torch.float32, device="cuda")
+    with pytest.raises(B.SpeedAnnError, match="multiple of 4"):
+        B._check(B.lib().sa_gather_probe(dev(w.base).data_ptr(), 20_000, 128, 128, 6, 64, 1, sink.data_ptr(), None),
+                 "sa_gather_probe")
