@@ -128,13 +128,15 @@ int sa_knn(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float 
  *                sums are all exact (each sum stays below 2^24 in magnitude), the squared
  *                distance |q|^2 + |x|^2 - 2 q.x is formed in 32-bit integers and rounded
  *                once to float32, and the keys equal the double-precision ones bit for bit.
- *                Other finite float data (d <= 128, k <= 96): coordinates split into bf16
+ *                Other finite float data (d <= 1024, k <= 96): coordinates split into bf16
  *                high and low parts, three products per block give approximate distances
- *                within a proven bound, each query keeps its k + 32 best candidates, and a
+ *                within a proven bound (L2 data are first moved by the base mean, which
+ *                leaves distances unchanged), each query keeps its 128 best candidates, and a
  *                second kernel rescores them with the scan's double-precision arithmetic;
- *                when the bound shows that no other point can enter the k best, the result
- *                is the scan's bit for bit, and when it cannot (many distances tied
- *                within the bound) the call runs the scan instead.  Either form copies
+ *                where the bound shows that no other point can enter a query's k best,
+ *                its row is the scan's bit for bit, and the queries for which it cannot
+ *                (many distances tied within the bound) are rescored by the scan alone
+ *                (sa_knn_last_rescanned counts them).  Either form copies
  *                base and queries to temporary bf16 arrays (hipMalloc, freed before
  *                returning) and checks the values on the device first.
  *   SA_KNN_AUTO  SA_KNN_MFMA when a form applies and succeeds, else SA_KNN_SCAN. */
@@ -146,6 +148,12 @@ typedef enum { SA_KNN_AUTO = 0, SA_KNN_SCAN = 1, SA_KNN_MFMA = 2 } sa_knn_path;
 int sa_knn_ex(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float *queries_dev, int64_t nq,
               int64_t ldq, int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids_dev, float *dists_dev,
               int32_t path, int32_t *path_used_out, void *hip_stream);
+
+/* The number of queries that the last sa_knn / sa_knn_ex call made on the calling thread
+ * handed from the float form of SA_KNN_MFMA to the scan because their candidate lists
+ * could not show the margin (0 when that form did not run).  Results are exact either
+ * way; the count only says how much of the call ran on the slower path. */
+int64_t sa_knn_last_rescanned(void);
 
 /* ------------------------------------------------------------------ graph construction
  * The paper searches a graph built offline (NSG, Sec. 2.2) and does not construct one.

@@ -25,7 +25,7 @@ EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_quan
            "sa_batch_tune", "sa_batch_set_config", "sa_batch_describe", "sa_server_default_config",
            "sa_server_create", "sa_server_destroy", "sa_server_submit", "sa_server_poll", "sa_server_replay",
            "sa_server_stats", "sa_graph_order", "sa_permute_rows", "sa_permute_graph", "sa_index_set_id_map",
-           "sa_gather_probe"]
+           "sa_gather_probe", "sa_knn_last_rescanned"]
 
 
 class SearchParams(C.Structure):
@@ -63,6 +63,8 @@ def lib():
         L.sa_default_params.argtypes = [C.POINTER(SearchParams)]
         L.sa_knn.argtypes = [vp, i64, i32, i64, vp, i64, i64, i32, i32, i32, vp, vp, vp]
         L.sa_knn_ex.argtypes = [vp, i64, i32, i64, vp, i64, i64, i32, i32, i32, vp, vp, i32, C.POINTER(C.c_int32), vp]
+        L.sa_knn_last_rescanned.argtypes = []
+        L.sa_knn_last_rescanned.restype = i64
         L.sa_medoid.argtypes = [vp, i64, i32, i64, C.POINTER(C.c_int32), vp]
         L.sa_prune.argtypes = [vp, i64, i32, i64, i32, vp, i32, i32, i32, vp, vp]
         L.sa_reverse_edges.argtypes = [vp, i64, i32, i64, i32, vp, i32, C.POINTER(C.c_int64), vp]
@@ -156,9 +158,9 @@ def knn(base: torch.Tensor, queries: torch.Tensor, k: int, metric="l2", exclude_
         path="auto", return_path=False):
     """Exact top-k by (distance, id) over all rows of base (linear scan on the GPU).
 
-    path: "scan" (double precision, any data), "mfma" (bf16 matrix cores, integer-valued
-    data only, exact), "auto" (mfma where it applies).  With return_path the path that
-    ran is returned as a third value."""
+    path: "scan" (double precision, any data), "mfma" (bf16 matrix cores: integer-valued
+    data, or finite floats with d <= 1024 and k <= 96; exact either way), "auto" (mfma
+    where it applies).  With return_path the path that ran is returned as a third value."""
     base = pad_dim(_mat(base, "base"))
     queries = base if (exclude_self and queries is None) else pad_dim(_mat(queries, "queries"))
     nq = queries.shape[0]
@@ -172,6 +174,11 @@ def knn(base: torch.Tensor, queries: torch.Tensor, k: int, metric="l2", exclude_
         names = {v: n for n, v in KNN_PATHS.items()}
         return ids, dists, names[int(used.value)]
     return ids, dists
+
+
+def knn_last_rescanned() -> int:
+    """Queries of the last knn call on this thread that the float MFMA form handed to the scan."""
+    return int(lib().sa_knn_last_rescanned())
 
 
 def medoid(base: torch.Tensor, stream=None) -> int:

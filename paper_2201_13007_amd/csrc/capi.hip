@@ -116,6 +116,8 @@ int sa_knn_ex(const float *base_dev, int64_t n, int32_t d, int64_t ld, const flo
                       path_used_out, (hipStream_t)hip_stream);
 }
 
+int64_t sa_knn_last_rescanned(void) { return knn_rescanned; }
+
 int sa_knn(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float *queries_dev, int64_t nq, int64_t ldq,
            int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids_dev, float *dists_dev, void *hip_stream)
 {

@@ -29,6 +29,7 @@ struct KnnArgs {
     const float *queries;
     int64_t nq, ldq;
     int32_t d, k, kpad, metric, exclude_self;
+    const int32_t *qmap;   // job j is query qmap[j] (its row, its self id, its output row); null: j
     int32_t *ids;
     float *dists;
 };
@@ -68,7 +69,8 @@ __global__ void __launch_bounds__(NT) knn_kernel(KnnArgs A)
             for (int i = tid; i < TQ * DC; i += NT) {
                 int r = i / DC, c = i % DC;
                 int64_t qr = q0 + r;
-                Qs[r * (DC + 1) + c] = (qr < A.nq && c < dlen) ? A.queries[qr * A.ldq + dc + c] : 0.f;
+                const int64_t qs = qr < A.nq && A.qmap ? A.qmap[qr] : qr;
+                Qs[r * (DC + 1) + c] = (qr < A.nq && c < dlen) ? A.queries[qs * A.ldq + dc + c] : 0.f;
             }
             for (int i = tid; i < TX * DC; i += NT) {
                 int r = i / DC, c = i % DC;
@@ -105,11 +107,12 @@ __global__ void __launch_bounds__(NT) knn_kernel(KnnArgs A)
             const int qr = tq + 16 * a;
             const int64_t qg = q0 + qr;
             if (qg >= A.nq) continue;
+            const int64_t self = A.qmap ? A.qmap[qg] : qg;
             const uint64_t t = thr[qr];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int64_t xg = xb + tx + 16 * b;
-                if (xg >= A.n || (A.exclude_self && xg == qg)) continue;
+                if (xg >= A.n || (A.exclude_self && xg == self)) continue;
                 const float dist = A.metric == SA_L2 ? (float)acc[a][b] : (float)(-acc[a][b]);
                 const uint64_t key = make_key(dist, (int32_t)xg);
                 if (key < t) {
@@ -141,13 +144,14 @@ __global__ void __launch_bounds__(NT) knn_kernel(KnnArgs A)
         const int qr = i / A.k, j = i % A.k;
         const int64_t qg = q0 + qr;
         if (qg >= A.nq) continue;
+        const int64_t orow = A.qmap ? A.qmap[qg] : qg;
         if (j < toplen[qr]) {
             const uint64_t key = top[(size_t)qr * A.kpad + j];
-            A.ids[qg * A.k + j] = key_id(key);
-            A.dists[qg * A.k + j] = key_dist(key);
+            A.ids[orow * A.k + j] = key_id(key);
+            A.dists[orow * A.k + j] = key_dist(key);
         } else {
-            A.ids[qg * A.k + j] = -1;
-            A.dists[qg * A.k + j] = __builtin_inff();
+            A.ids[orow * A.k + j] = -1;
+            A.dists[orow * A.k + j] = __builtin_inff();
         }
     }
 }
@@ -155,12 +159,14 @@ __global__ void __launch_bounds__(NT) knn_kernel(KnnArgs A)
 }  // namespace
 
 int launch_knn_scan(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq, int64_t ldq,
-               int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists, hipStream_t stream)
+               int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists, hipStream_t stream,
+               const int32_t *qmap)
 {
     if (nq == 0) return SA_OK;
     KnnArgs A;
     A.base = base; A.n = n; A.ld = ld; A.queries = queries; A.nq = nq; A.ldq = ldq;
     A.d = d; A.k = k; A.metric = metric; A.exclude_self = exclude_self; A.ids = ids; A.dists = dists;
+    A.qmap = qmap;
     A.kpad = (k + 63) / 64 * 64;
     size_t lds = sizeof(float) * (size_t)(TQ + TX) * (DC + 1);
     lds = (lds + 15) / 16 * 16;

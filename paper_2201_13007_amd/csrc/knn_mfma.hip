@@ -21,17 +21,20 @@
 // build a 64-bit key and enter the query's LDS buffer, which is sorted and merged into
 // the query's top-k list as in the scan.
 //
-// Float data (d <= 128, k <= 96).  Each coordinate is split into bf16 parts x = h + l + r
-// (h = bf16(x), l = bf16(x - h), |r| <= 2^-16 |x|, 2^-14 if conversions truncated) and
+// Float data (d <= 1024, k <= 96; above d = 128 the chunks of 32 dimensions are loaded per
+// tile instead of held in registers).  Each coordinate is split into bf16 parts x = h + l + r
+// (h and l rounded to nearest even, so |x - h| <= 2^-8 |x| and |r| <= 2^-16 |x|) and
 // q.x is approximated by qh.xh + qh.xl + ql.xh on the matrix cores with fp32 accumulation.
-// Its error is at most c |q| |x| with c = 3.1 2^-14 + (3d + 2) 2^-24 (the omitted terms,
+// Its error is at most c |q| |x| with c = 3.1 2^-16 + (3d + 2) 2^-24 (the omitted terms,
 // then every fp32 rounding of the 3d products), so every approximate distance is within E_q of the exact
-// one, with E_q from |q| and the largest |x| (doubled for safety).  The candidate kernel
-// keeps the kc = k + 32 smallest approximate keys; if the kc-th approximate distance
-// exceeds the k-th by more than 2 E_q, no point outside the list can be among the k
-// nearest, and the exact kernel rescores the kc candidates with the scan's own FP64
-// arithmetic and keeps the k smallest exact keys: the scan's result, bit for bit.  If a
-// query's list cannot show that margin, the whole call falls back to the scan.
+// one, with E_q from |q| and the largest |x| (doubled for safety).  For L2 all points are
+// first moved by the base mean (distances unchanged, norms and so the bound smaller).  The
+// candidate kernel keeps the kc = 128 smallest approximate keys; the exact kernel rescores
+// them with the scan's own FP64 arithmetic and keeps the k smallest exact keys.  Every
+// point outside the list is then at least (kc-th approximate distance - E_q) away; if
+// that exceeds the k-th exact key, none can enter the k best, and the result is the
+// scan's, bit for bit.  The queries that cannot show that margin (ties within the bound)
+// are listed and rescored by the scan alone.
 #include "knn_select.h"
 
 #include <climits>
@@ -248,12 +251,33 @@ __global__ void __launch_bounds__(MNT) knn_mfma_kernel(MArgs A)
 
 // ---------------------------------------------------------------- float data
 
-constexpr int KC_EXTRA = 32;   // candidates kept beyond k
+constexpr int KC = 128;        // candidates kept per query (k <= 96)
+
+// column sums of the base in double (L2 centring): one block per row chunk
+__global__ void __launch_bounds__(256) knn_colsum_kernel(const float *x, int64_t n, int d, int64_t ld, int64_t chunk,
+                                                         double *sum)
+{
+    const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = r0 + chunk < n ? r0 + chunk : n;
+    for (int c = threadIdx.x; c < d; c += blockDim.x) {
+        double acc = 0.0;
+        for (int64_t r = r0; r < r1; ++r) acc += (double)x[r * ld + c];
+        atomicAdd(sum + c, acc);
+    }
+}
+
+// float -> bf16 bits, rounded to nearest even (finite inputs; an overflow rounds to inf)
+__device__ __forceinline__ uint16_t bf16_rne_bits(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
 
 struct FPrepArgs {
     const float *x;
     int64_t n, ld, rows;
     int32_t d, dpad;
+    const double *colsum;  // L2: subtract colsum / n_base from every coordinate (null: none)
+    double n_base;
     __bf16 *hi, *lo;      // rows x dpad
     float *norm2;         // rows: |x|^2 (rounded once from double)
     unsigned *max_norm2;  // bits of the largest |x|^2 (non-negative floats order as unsigned)
@@ -274,10 +298,12 @@ __global__ void __launch_bounds__(256) knn_prep_float_kernel(FPrepArgs P)
             bad = true;
             v = 0.f;
         }
-        const __bf16 h = (__bf16)v;
-        const __bf16 l = (__bf16)(v - (float)h);
-        P.hi[row * P.dpad + c] = h;
-        P.lo[row * P.dpad + c] = l;
+        if (P.colsum && row < P.n && c < P.d) v -= (float)(P.colsum[c] / P.n_base);
+        const uint16_t hb = bf16_rne_bits(v);
+        const float hf = __uint_as_float((uint32_t)hb << 16);
+        const uint16_t lb = bf16_rne_bits(v - hf);   // v - hf is exact
+        P.hi[row * P.dpad + c] = __builtin_bit_cast(__bf16, hb);
+        P.lo[row * P.dpad + c] = __builtin_bit_cast(__bf16, lb);
         sum += (double)v * (double)v;
     }
     for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
@@ -440,12 +466,16 @@ struct EArgs {
     const unsigned *max_norm2;
     int32_t *ids;
     float *dists;
-    int32_t *failed;            // queries whose list could not show the margin
+    int32_t *failed;            // count of queries whose list could not show the margin
+    int32_t *failed_list;       // those queries, in any order
 };
 
-// One wavefront per query: the margin test, then the exact keys of the candidates with
-// the scan's arithmetic (double, index order, separately rounded multiply and add, one
-// rounding to float) and the k smallest.
+// One wavefront per query: the exact keys of the candidates with the scan's arithmetic
+// (double, index order, separately rounded multiply and add, one rounding to float) and
+// the k smallest, then the margin test.  A point outside the list has an approximate
+// distance of at least the list's last one, so its exact distance is at least that less
+// E_q; if that exceeds the k-th exact key by more than a few float units (the keys are
+// roundings), no outside point can enter the k best.
 __global__ void __launch_bounds__(64) knn_exact_kernel(EArgs E)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -454,18 +484,6 @@ __global__ void __launch_bounds__(64) knn_exact_kernel(EArgs E)
     const int64_t q = blockIdx.x;
     const int nc = E.cand_len[q];
     const int32_t *cd = E.cand + q * E.kc;
-    if (nc >= E.kc) {
-        // (2^-14 rather than 2^-16: the bound holds even for truncating bf16 conversions)
-        const double c = 3.1 / 16384.0 + (3.0 * E.d + 2.0) / 16777216.0;
-        const double nq_ = sqrt((double)E.qn[q]), nm = sqrt((double)__uint_as_float(*E.max_norm2));
-        const double err = E.metric == SA_L2 ? 2.0 * (2.0 * c * nq_ * nm + 4.0 / 16777216.0 * (nq_ + nm) * (nq_ + nm))
-                                             : 2.0 * (c * nq_ * nm + 2.0 / 16777216.0 * nq_ * nm);
-        const double dk = E.cand_d[q * E.kc + E.k - 1], dl = E.cand_d[q * E.kc + E.kc - 1];
-        if (!(dl > dk + 2.0 * err)) {
-            if (lane == 0) atomicAdd(E.failed, 1);
-            return;
-        }
-    }
     for (int c = lane; c < E.d; c += 64) qs[c] = E.queries[q * E.ldq + c];
     __builtin_amdgcn_wave_barrier();
     unsigned long long key[2];
@@ -489,6 +507,21 @@ __global__ void __launch_bounds__(64) knn_exact_kernel(EArgs E)
         }
     }
     knn_detail::sort128(key[0], key[1]);
+    if (nc >= E.kc) {
+        // (for L2 the last term also covers the rounding of the centred coordinates)
+        const double c = 3.1 / 65536.0 + (3.0 * E.d + 2.0) / 16777216.0;
+        const double nq_ = sqrt((double)E.qn[q]), nm = sqrt((double)__uint_as_float(*E.max_norm2));
+        const double err = E.metric == SA_L2 ? 2.0 * (2.0 * c * nq_ * nm + 8.0 / 16777216.0 * (nq_ + nm) * (nq_ + nm))
+                                             : 2.0 * (c * nq_ * nm + 2.0 / 16777216.0 * nq_ * nm);
+        const int kk = E.k - 1;
+        const unsigned long long kth = __shfl(kk < 64 ? key[0] : key[1], kk & 63, 64);
+        const double Kk = key_dist(kth);
+        const double last = E.cand_d[q * E.kc + E.kc - 1];
+        if (!(last - err > Kk + fabs(Kk) * (1.0 / 1048576.0))) {
+            if (lane == 0) E.failed_list[atomicAdd(E.failed, 1)] = (int32_t)q;
+            return;
+        }
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int j = lane + 64 * h;
@@ -497,6 +530,128 @@ __global__ void __launch_bounds__(64) knn_exact_kernel(EArgs E)
             E.ids[q * E.k + j] = ok ? key_id(key[h]) : -1;
             E.dists[q * E.k + j] = ok ? key_dist(key[h]) : __builtin_inff();
         }
+    }
+}
+
+// The candidate pass for larger d (128 < d <= 1024): the same products, with the query
+// and base parts of each 32-dimension chunk loaded per tile (queries from the caches,
+// the next chunk's operands in flight while the current chunk's products run).
+template <bool L2>
+__global__ void __launch_bounds__(MNT) knn_mfma_float_kloop_kernel(FArgs A)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    uint64_t *top = reinterpret_cast<uint64_t *>(smem);
+    uint64_t *buf = top + (size_t)MQ * A.kpad;
+    uint64_t *thr = buf + (size_t)MQ * MBUF;
+    int *cnt = reinterpret_cast<int *>(thr + MQ);
+    int *len = cnt + MQ;
+    float *qns = reinterpret_cast<float *>(len + MQ);
+    int *need = reinterpret_cast<int *>(qns + MQ);
+
+    const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+    const int64_t q0 = (int64_t)blockIdx.x * MQ;
+    for (int i = tid; i < MQ; i += MNT) {
+        cnt[i] = 0;
+        len[i] = 0;
+        thr[i] = q0 + i < A.nq ? KEY_EMPTY : 0ull;
+        qns[i] = A.qn[q0 + i];
+    }
+    if (tid == 0) *need = 0;
+    __syncthreads();
+
+    const int nks = A.dpad / 32;
+    const int64_t ntile = A.xrows / MT;
+    const int koff = 8 * (lane >> 4);
+    int64_t qoff[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) qoff[rb] = (q0 + rb * 16 + (lane & 15)) * A.dpad + koff;
+    for (int64_t t = 0; t < ntile; ++t) {
+        const int64_t xoff = (t * MT + 16 * w + (lane & 15)) * A.dpad + koff;
+        f32x4 acc[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        bf16x8 ah[2][4], al[2][4], bh[2], bl[2];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            ah[0][rb] = *reinterpret_cast<const bf16x8 *>(A.qh + qoff[rb]);
+            al[0][rb] = *reinterpret_cast<const bf16x8 *>(A.ql + qoff[rb]);
+        }
+        bh[0] = *reinterpret_cast<const bf16x8 *>(A.xh + xoff);
+        bl[0] = *reinterpret_cast<const bf16x8 *>(A.xl + xoff);
+        for (int ks = 0; ks < nks; ks += 2) {
+            // chunk ks + 1 in flight while chunk ks multiplies, then the other way round
+            const int k1 = ks + 1 < nks ? ks + 1 : ks;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                ah[1][rb] = *reinterpret_cast<const bf16x8 *>(A.qh + qoff[rb] + 32 * k1);
+                al[1][rb] = *reinterpret_cast<const bf16x8 *>(A.ql + qoff[rb] + 32 * k1);
+            }
+            bh[1] = *reinterpret_cast<const bf16x8 *>(A.xh + xoff + 32 * k1);
+            bl[1] = *reinterpret_cast<const bf16x8 *>(A.xl + xoff + 32 * k1);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[0][rb], bh[0], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[0][rb], bl[0], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[0][rb], bh[0], acc[rb], 0, 0, 0);
+            }
+            if (ks + 1 >= nks) break;
+            const int k2 = ks + 2 < nks ? ks + 2 : ks + 1;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                ah[0][rb] = *reinterpret_cast<const bf16x8 *>(A.qh + qoff[rb] + 32 * k2);
+                al[0][rb] = *reinterpret_cast<const bf16x8 *>(A.ql + qoff[rb] + 32 * k2);
+            }
+            bh[0] = *reinterpret_cast<const bf16x8 *>(A.xh + xoff + 32 * k2);
+            bl[0] = *reinterpret_cast<const bf16x8 *>(A.xl + xoff + 32 * k2);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[1][rb], bh[1], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[1][rb], bl[1], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[1][rb], bh[1], acc[rb], 0, 0, 0);
+            }
+        }
+        const int64_t col = t * MT + 16 * w + (lane & 15);
+        const float nx = A.xn[t * MT + 16 * w + (lane & 15)];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rb * 16 + 4 * (lane >> 4) + r;
+                if (col < A.n && !(A.exclude_self && col == q0 + row)) {
+                    const float dt = L2 ? (qns[row] + nx) - 2.f * acc[rb][r] : -acc[rb][r];
+                    const uint64_t key = make_key(dt, (int32_t)col);
+                    if (key < thr[row]) {
+                        const int pos = atomicAdd(&cnt[row], 1);
+                        buf[(size_t)row * MBUF + pos] = key;
+                        if (pos + 1 > MBUF - MT) *need = (int)(t + 1);
+                    }
+                }
+            }
+        __syncthreads();
+        const bool last = t + 1 == ntile;
+        if (*need == (int)(t + 1) || last) {
+            for (int qr = w; qr < MQ; qr += MNT / 64) {
+                const int c = cnt[qr];
+                if (c == 0) continue;
+                flush_query(top + (size_t)qr * A.kpad, &len[qr], buf + (size_t)qr * MBUF, c, A.kc);
+                __builtin_amdgcn_wave_barrier();
+                if (lane == 0) {
+                    cnt[qr] = 0;
+                    if (len[qr] >= A.kc) thr[qr] = top[(size_t)qr * A.kpad + A.kc - 1];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < MQ * A.kc; i += MNT) {
+        const int qr = i / A.kc, j = i % A.kc;
+        const int64_t qg = q0 + qr;
+        if (qg >= A.nq) continue;
+        const bool ok = j < len[qr];
+        const uint64_t key = ok ? top[(size_t)qr * A.kpad + j] : KEY_EMPTY;
+        A.cand[qg * A.kc + j] = ok ? key_id(key) : -1;
+        A.cand_d[qg * A.kc + j] = ok ? key_dist(key) : __builtin_inff();
+        if (j == 0) A.cand_len[qg] = len[qr];
     }
 }
 
@@ -509,7 +664,7 @@ FKernel pick_float_kernel(int ks, int metric)
     case 2: return metric == SA_L2 ? knn_mfma_float_kernel<2, true> : knn_mfma_float_kernel<2, false>;
     case 3: return metric == SA_L2 ? knn_mfma_float_kernel<3, true> : knn_mfma_float_kernel<3, false>;
     case 4: return metric == SA_L2 ? knn_mfma_float_kernel<4, true> : knn_mfma_float_kernel<4, false>;
-    default: return nullptr;
+    default: return metric == SA_L2 ? knn_mfma_float_kloop_kernel<true> : knn_mfma_float_kloop_kernel<false>;
     }
 }
 
@@ -605,8 +760,9 @@ int launch_knn_mfma(const float *base, int64_t n, int32_t d, int64_t ld, const f
     return SA_OK;
 }
 
-// The float path for d <= 128 and k <= 96; *ran is false when it cannot show every
-// query's margin (the caller then runs the scan).  Synchronous.
+// The float path for d <= 1024 and k <= 96; *ran is false on non-finite data (the caller
+// then runs the scan).  Queries that cannot show their margin are rescored by the scan
+// here.  Synchronous.
 int launch_knn_mfma_float(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq,
                           int64_t ldq, int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists,
                           bool *ran, hipStream_t s)
@@ -614,15 +770,16 @@ int launch_knn_mfma_float(const float *base, int64_t n, int32_t d, int64_t ld, c
     *ran = false;
     const int ks = (d + 31) / 32;
     const int dpad = 32 * ks;
-    const int kc = k + KC_EXTRA;
+    const int kc = KC;
     const int64_t xrows = (n + MT - 1) / MT * MT;
     const bool shared_q = queries == base && ldq == ld && nq <= n;
     const int64_t qrows = shared_q ? xrows : (nq + MQ - 1) / MQ * MQ;
     const size_t xp = align256((size_t)xrows * dpad * 2), xn_b = align256((size_t)xrows * 4);
     const size_t qp = shared_q ? 0 : align256((size_t)qrows * dpad * 2), qn_b = shared_q ? 0 : align256((size_t)qrows * 4);
     const size_t cand_b = align256((size_t)nq * kc * 4), len_b = align256((size_t)nq * 4);
+    const size_t mu_b = align256((size_t)d * 8);
     DeviceBlock mem;
-    const size_t total = 2 * xp + xn_b + 2 * qp + qn_b + 2 * cand_b + len_b + 256;
+    const size_t total = 2 * xp + xn_b + 2 * qp + qn_b + 2 * cand_b + 2 * len_b + mu_b + 256;
     if (hipMalloc(&mem.p, total) != hipSuccess) {
         (void)hipGetLastError();
         mem.p = nullptr;
@@ -638,14 +795,28 @@ int launch_knn_mfma_float(const float *base, int64_t n, int32_t d, int64_t ld, c
     int32_t *cand = reinterpret_cast<int32_t *>(m); m += cand_b;
     float *cand_d = reinterpret_cast<float *>(m); m += cand_b;
     int32_t *cand_len = reinterpret_cast<int32_t *>(m); m += len_b;
+    int32_t *failed_list = reinterpret_cast<int32_t *>(m); m += len_b;
+    double *colsum = reinterpret_cast<double *>(m); m += mu_b;
     unsigned *flags = reinterpret_cast<unsigned *>(m);   // [0] max |x|^2, [1] bad, [2] failed, [3] unused norm
     SA_HIP(hipMemsetAsync(flags, 0, 16, s));
-    FPrepArgs P{base, n, ld, xrows, d, dpad, xh, xl, xn, flags, reinterpret_cast<int32_t *>(flags + 1)};
+    const double *mu = nullptr;
+    if (metric == SA_L2) {
+        // distances do not change when every point moves by the base mean, and the bound,
+        // which grows with the norms, shrinks
+        SA_HIP(hipMemsetAsync(colsum, 0, (size_t)d * 8, s));
+        const int64_t chunk = (n + 4095) / 4096;
+        hipLaunchKernelGGL(knn_colsum_kernel, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(256), 0, s, base, n, d,
+                           ld, chunk, colsum);
+        SA_HIP(hipGetLastError());
+        mu = colsum;
+    }
+    FPrepArgs P{base, n, ld, xrows, d, dpad, mu, (double)n, xh, xl, xn, flags, reinterpret_cast<int32_t *>(flags + 1)};
     hipLaunchKernelGGL(knn_prep_float_kernel, dim3((unsigned)((xrows + 3) / 4)), dim3(256), 0, s, P);
     SA_HIP(hipGetLastError());
     if (!shared_q) {
         // queries do not take part in the largest |x|: their maximum goes to an unused word
-        FPrepArgs Q{queries, nq, ldq, qrows, d, dpad, qh, ql, qn, flags + 3, reinterpret_cast<int32_t *>(flags + 1)};
+        FPrepArgs Q{queries, nq, ldq, qrows, d, dpad, mu, (double)n, qh, ql, qn, flags + 3,
+                    reinterpret_cast<int32_t *>(flags + 1)};
         hipLaunchKernelGGL(knn_prep_float_kernel, dim3((unsigned)((qrows + 3) / 4)), dim3(256), 0, s, Q);
         SA_HIP(hipGetLastError());
     }
@@ -662,52 +833,63 @@ int launch_knn_mfma_float(const float *base, int64_t n, int32_t d, int64_t ld, c
     hipLaunchKernelGGL(kern, dim3((unsigned)((nq + MQ - 1) / MQ)), dim3(MNT), lds, s, A);
     SA_HIP(hipGetLastError());
     EArgs E{base, n, ld, queries, nq, ldq, d, k, kc, metric, cand, cand_d, cand_len, qn, flags, ids, dists,
-            reinterpret_cast<int32_t *>(flags + 2)};
+            reinterpret_cast<int32_t *>(flags + 2), failed_list};
     hipLaunchKernelGGL(knn_exact_kernel, dim3((unsigned)nq), dim3(64), 4 * (size_t)dpad, s, E);
     SA_HIP(hipGetLastError());
     unsigned hf[3] = {0, 0, 0};
     SA_HIP(hipMemcpyAsync(hf, flags, 12, hipMemcpyDeviceToHost, s));
     SA_HIP(hipStreamSynchronize(s));
-    *ran = hf[1] == 0 && hf[2] == 0;
+    if (hf[1] != 0) return SA_OK;
+    if (hf[2] > 0) {
+        // the listed queries' rows are written by the scan; every other row is final
+        const int rc = launch_knn_scan(base, n, d, ld, queries, (int64_t)hf[2], ldq, k, metric, exclude_self, ids,
+                                       dists, s, failed_list);
+        if (rc != SA_OK) return rc;
+        SA_HIP(hipStreamSynchronize(s));
+        knn_rescanned = hf[2];
+    }
+    *ran = true;
     return SA_OK;
 }
 
 }  // namespace
+
+thread_local int64_t knn_rescanned = 0;
 
 int launch_knn(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq, int64_t ldq,
                int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists, int32_t path,
                int32_t *path_used, hipStream_t stream)
 {
     if (path_used) *path_used = SA_KNN_AUTO;
+    knn_rescanned = 0;
     if (path != SA_KNN_AUTO && path != SA_KNN_SCAN && path != SA_KNN_MFMA)
         return set_error(SA_EINVAL, "unknown kNN path %d", path);
     if (nq == 0) return SA_OK;
-    const bool shape_ok = n >= 1 && d <= 256 && k <= 128;
-    if (path == SA_KNN_MFMA && !shape_ok)
-        return set_error(SA_EUNSUPPORTED, "the MFMA kNN path needs n >= 1, d <= 256 and k <= 128 (n=%lld, d=%d, k=%d)",
-                         (long long)n, d, k);
-    if (path != SA_KNN_SCAN && shape_ok) {
+    const bool int_shape = n >= 1 && d <= 256 && k <= 128;    // integer-valued data
+    const bool flt_shape = n >= 1 && d <= 1024 && k <= 96;    // any finite data
+    if (path == SA_KNN_MFMA && !int_shape && !flt_shape)
+        return set_error(SA_EUNSUPPORTED, "the MFMA kNN path needs n >= 1 and d <= 256, k <= 128 (integer data) or "
+                         "d <= 1024, k <= 96 (n=%lld, d=%d, k=%d)", (long long)n, d, k);
+    if (path != SA_KNN_SCAN) {
         bool ran = false;
-        const int rc = launch_knn_mfma(base, n, d, ld, queries, nq, ldq, k, metric, exclude_self, ids, dists, &ran,
-                                       stream);
-        if (rc != SA_OK) return rc;
+        if (int_shape) {
+            const int rc = launch_knn_mfma(base, n, d, ld, queries, nq, ldq, k, metric, exclude_self, ids, dists,
+                                           &ran, stream);
+            if (rc != SA_OK) return rc;
+        }
+        // not integer data (or too wide for it): the float path, where its shape allows
+        if (!ran && flt_shape) {
+            const int rf = launch_knn_mfma_float(base, n, d, ld, queries, nq, ldq, k, metric, exclude_self, ids,
+                                                 dists, &ran, stream);
+            if (rf != SA_OK) return rf;
+        }
         if (ran) {
             if (path_used) *path_used = SA_KNN_MFMA;
             return SA_OK;
         }
-        // not integer data: the float path, where its shape allows
-        if (d <= 128 && k <= 96 && n >= 1) {
-            const int rf = launch_knn_mfma_float(base, n, d, ld, queries, nq, ldq, k, metric, exclude_self, ids,
-                                                 dists, &ran, stream);
-            if (rf != SA_OK) return rf;
-            if (ran) {
-                if (path_used) *path_used = SA_KNN_MFMA;
-                return SA_OK;
-            }
-        }
         if (path == SA_KNN_MFMA)
             return set_error(SA_EUNSUPPORTED, "the MFMA kNN path needs integer coordinates in [-255, 255] (d <= 256, "
-                             "k <= 128) or finite floats with d <= 128 and k <= 96 whose candidates separate");
+                             "k <= 128) or finite floats with d <= 1024 and k <= 96");
     }
     const int rc = launch_knn_scan(base, n, d, ld, queries, nq, ldq, k, metric, exclude_self, ids, dists, stream);
     if (rc != SA_OK) return rc;

@@ -59,10 +59,14 @@ __host__ __device__ inline float key_dist(uint64_t k) { return ordered_to_float(
 int launch_knn(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq, int64_t ldq,
                int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists, int32_t path,
                int32_t *path_used, hipStream_t stream);
-// The double-precision scan (any data); enqueued only.
+// The double-precision scan (any data); enqueued only.  With qmap, job j is query qmap[j]
+// (its row, its excluded self id and its output row).
 int launch_knn_scan(const float *base, int64_t n, int32_t d, int64_t ld, const float *queries, int64_t nq,
                     int64_t ldq, int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids, float *dists,
-                    hipStream_t stream);
+                    hipStream_t stream, const int32_t *qmap = nullptr);
+// Queries that the last launch_knn on this thread handed from the MFMA float path to the
+// scan because they could not show their margin.
+extern thread_local int64_t knn_rescanned;
 
 struct SearchLaunch {
     const void *codes;     // stored vectors (float32, bf16 or fp8 codes), rows of ldc elements

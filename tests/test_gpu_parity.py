@@ -146,7 +146,7 @@ def test_knn_paths_agree_sift(B):
 
 
 def test_knn_path_selection(B):
-    # float data with d <= 128 and k <= 96 runs on the matrix cores (bf16 hi/lo products
+    # float data with d <= 1024 and k <= 96 runs on the matrix cores (bf16 hi/lo products
     # rescored in double); the result is the oracle's whichever path runs
     w = synth.tiny()
     print("case: knn path selection", flush=True)
@@ -156,17 +156,18 @@ def test_knn_path_selection(B):
     np.testing.assert_array_equal(host(ids), eids)
     np.testing.assert_array_equal(host(dd), ed)
     g = synth.integer_grid(700, 16, 9, config=93)
-    wide = synth.tiny(n=600, nq=5, d=200)
-    # half-integers and integers beyond 255 leave the integer path; their many exact ties
-    # may keep the float path from separating its candidates, and then the scan runs
+    wide = synth.tiny(n=600, nq=5, d=1100)
+    # half-integers and integers beyond 255 leave the integer path for the float one; the
+    # queries whose exact ties keep their candidates from separating are rescored by the scan
     for base, q, k in ((g.base * 0.5, g.queries, 10), (g.base + 250.0, g.queries, 10)):
         ids, dd, used = B.knn(dev(base), dev(q), k, return_path=True)
-        assert used in ("mfma", "scan")
+        assert used == "mfma"
+        assert 0 <= B.knn_last_rescanned() <= q.shape[0]
         eids, ed = oracle.knn(base, q, k)
         np.testing.assert_array_equal(host(ids), eids)
         np.testing.assert_array_equal(host(dd), ed)
-    # beyond both matrix-core paths: d > 128 with float data, k > 128
-    for base, q, k, why in ((wide.base, wide.queries, 10, "d <= 128"), (g.base, g.queries, 129, "k <= 128")):
+    # beyond both matrix-core paths: d > 1024 with float data, k > 128
+    for base, q, k, why in ((wide.base, wide.queries, 10, "d <= 1024"), (g.base, g.queries, 129, "k <= 128")):
         ids, dd, used = B.knn(dev(base), dev(q), k, return_path=True)
         assert used == "scan"
         eids, ed = oracle.knn(base, q, k)
@@ -391,13 +392,16 @@ def test_workspace_stays_zero_and_reusable(B, sift_setup):
         np.testing.assert_array_equal(host(r.stats)[:, 3], est["dist_comps"])
 
 
-@pytest.mark.parametrize("case", ["deep-ip", "uniform-l2", "deep-self-l2", "k96", "k1"])
+@pytest.mark.parametrize("case", ["deep-ip", "uniform-l2", "deep-self-l2", "k96", "k1", "gist-self-d960"])
 def test_knn_float_mfma_equals_scan(B, case):
     # float data on the matrix cores: candidates from bf16 hi/lo products, rescored in
     # double; the result must be the scan's bit for bit, and the path must be the MFMA one
     if case == "uniform-l2":
         w = synth.tiny(n=7000, nq=90)
         base, q, metric, k, excl = w.base, w.queries, "l2", 16, False
+    elif case == "gist-self-d960":
+        w = synth.gist_like(n=5000, nq=1)
+        base, q, metric, k, excl = w.base, None, "l2", 64, True
     else:
         w = synth.deep_like(n=9000, nq=70)
         base, q = w.base, w.queries
@@ -416,6 +420,44 @@ def test_knn_float_mfma_equals_scan(B, case):
     if case == "k1":
         eids, ed = oracle.knn(base, q, k, metric=metric)
         np.testing.assert_array_equal(host(ids), eids)
+
+
+@pytest.mark.parametrize("self_join", [False, True])
+def test_knn_float_rescan_ties(B, self_join):
+    # 300 copies of one row: the queries at that row see more than 128 points tied within
+    # the bound, cannot show their margin and are rescored by the scan alone (with their
+    # own self id when the queries are the base rows); every other query stays on the
+    # matrix cores, and the whole result is the scan's bit for bit
+    w = synth.deep_like(n=6000, nq=40)
+    base = w.base.copy()
+    base[1:301] = base[0]
+    if self_join:
+        q, k = None, 20
+    else:
+        q = w.queries.copy()
+        q[[3, 17]] = base[0] + np.float32(1e-3)
+        k = 32
+    print(f"case: knn float rescan of tied queries self_join={self_join}", flush=True)
+    qd = None if q is None else dev(q)
+    ids, d, path = B.knn(dev(base), qd, k, exclude_self=self_join, return_path=True)
+    nres = B.knn_last_rescanned()
+    sids, sd = B.knn(dev(base), qd, k, exclude_self=self_join, path="scan")
+    assert B.knn_last_rescanned() == 0
+    assert path == "mfma"
+    nq = base.shape[0] if self_join else q.shape[0]
+    if self_join:
+        assert 301 <= nres < nq
+    else:
+        assert 2 <= nres < nq
+    np.testing.assert_array_equal(host(ids), host(sids))
+    np.testing.assert_array_equal(host(d), host(sd))
+    rows = np.array([0, 5, 150, 300, 301, 5999] if self_join else [3, 17, 0, 39])
+    if self_join:
+        eids, ed = oracle.knn_self(base, rows, k)
+    else:
+        eids, ed = oracle.knn(base, q[rows], k)
+    np.testing.assert_array_equal(host(ids)[rows], eids)
+    np.testing.assert_array_equal(host(d)[rows], ed)
 
 
 def test_gather_probe(B):
