@@ -52,7 +52,8 @@ sys.path.insert(0, ROOT)
 if "--workload" in sys.argv and ("serve" in sys.argv or "gist" in sys.argv):
     os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
-L_SWEEP = [32, 48, 64, 96, 128, 160, 192, 224, 256, 288, 320, 352, 384, 448, 512]
+L_SWEEP = [32, 48, 64, 80, 96, 112, 128, 144, 160, 176, 192, 208, 224, 240, 256, 272, 288, 304, 320, 336, 352, 384,
+           416, 448, 480, 512]
 M_SWEEP = [1, 2, 4, 8, 16]
 TARGET = 0.99
 HBM_PEAK_GBS = 8000.0
@@ -95,9 +96,10 @@ def load_traffic(workload_key):
     return t
 
 
-def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors"):
+def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors", lockstep=None):
     """The oracle's search timed on the host cores over a growing prefix of the queries
-    until about `seconds` of CPU work."""
+    until about `seconds` of CPU work.  lockstep=(M2, L2): also the one-thread latency of
+    the oracle at that point (Algorithm 3 with M2 workers, emulated in sequence)."""
     import oracle
     adj_h = adj.cpu().numpy()
     nq = w.queries.shape[0]
@@ -131,6 +133,17 @@ def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors"):
            "latency_p50_ms": round(float(np.percentile(lat, 50)), 4),
            "latency_p99_ms": round(float(np.percentile(lat, 99)), 4),
            "latency_sample": f"first {len(lat)} queries one at a time, one thread, host wall time"}
+    if lockstep is not None and tuple(lockstep) != (M, L):
+        M2, L2 = lockstep
+        lat2 = []
+        for i in range(min(50, nq)):
+            s0 = time.perf_counter()
+            oracle.speedann(w.base, adj_h, entry, w.queries[i:i + 1], k, L2, M2, sync="adaptive", rho=0.8,
+                            staged=True, metric=w.metric)
+            lat2.append((time.perf_counter() - s0) * 1e3)
+        cpu["lockstep_point"] = {"M": int(M2), "L": int(L2), "queries": len(lat2),
+                                 "latency_p50_ms": round(float(np.percentile(lat2, 50)), 4),
+                                 "latency_p99_ms": round(float(np.percentile(lat2, 99)), 4)}
     log(f"cpu oracle: {cpu['value']} q/s on {nthreads} threads ({done} queries, {t_cpu:.1f}s)")
     return cpu
 
@@ -814,7 +827,7 @@ def main():
                 "frac_of_gather_ceiling": round(achieved / gc["GBs"], 4)}
 
     # ---------------------------------------------------------------- CPU oracle baseline
-    cpu = None if args.no_cpu else cpu_oracle(w, adj0, entry0, k, L, M, args.cpu_seconds)
+    cpu = None if args.no_cpu else cpu_oracle(w, adj0, entry0, k, L, M, args.cpu_seconds, lockstep=(Mlat, Llat))
 
     res = {
         "metric": "QPS and p50/p99 latency at recall@10=0.99, 1M×128 SIFT-shaped, 1 GPU",

@@ -306,7 +306,8 @@ int sa_gather_probe(const float *vec_dev, int64_t n, int32_t d, int64_t ld, int6
  * params, whatever the batch holds and however it is tuned.
  *
  * The plan groups the queries into classes of equal M and equal register-queue size
- * (ceil(L / 64) rounded up to 1, 2, 4, 6, 8 or 16), one kernel launch each, longest L
+ * (ceil(L / 64), rounded up to 1-8 or 16 when M = 1 and to 1, 2, 4, 6, 8 or 16 when
+ * M >= 2), one kernel launch each, longest L
  * first within a class; classes go to up to eight internal streams (each wants a
  * hardware queue of its own: GPU_MAX_HW_QUEUES, default 4).  sa_batch_run only
  * enqueues kernel launches and event records and waits, so it can be captured in a HIP

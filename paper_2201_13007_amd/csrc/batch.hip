@@ -3,7 +3,8 @@
 //
 // Queries are grouped into classes by walker count M (the general kernel runs M
 // wavefronts per workgroup) and by the register-queue size the kernels are compiled for
-// (ceil(L / 64) rounded up to 1, 2, 4, 6, 8 or 16 slots per lane).  A class is one
+// (ceil(L / 64) slots per lane, rounded up to 1-8 or 16 for one walker and to 1, 2, 4,
+// 6, 8 or 16 for more).  A class is one
 // launch with one workgroup per query; it takes its queries longest L first, so the
 // hardware dispatcher, which hands out workgroups in index order as slots free up, runs
 // the long searches first and the short ones fill the tail.  Classes are spread over up
@@ -26,7 +27,7 @@ constexpr int MAX_STREAMS = 8;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int ni_bucket(int L) { return queue_slots_bucket(L); }
+int ni_bucket(int L, int M) { return queue_slots_bucket(L, M); }
 
 struct BatchClass {
     int32_t M, ni, Lmax, kmax;
@@ -178,7 +179,7 @@ int sa_batch_create(const sa_index *index, int64_t nq, const int32_t *L, const i
     for (int64_t q = 0; q < nq; ++q) idx[q] = (int32_t)q;
     std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t c) {
         if (M[a] != M[c]) return M[a] < M[c];
-        const int na = ni_bucket(L[a]), nc = ni_bucket(L[c]);
+        const int na = ni_bucket(L[a], M[a]), nc = ni_bucket(L[c], M[c]);
         if (na != nc) return na < nc;
         return L[a] > L[c];
     });
@@ -191,13 +192,13 @@ int sa_batch_create(const sa_index *index, int64_t nq, const int32_t *L, const i
         const int32_t q0 = idx[i];
         BatchClass c{};
         c.M = M[q0];
-        c.ni = ni_bucket(L[q0]);
+        c.ni = ni_bucket(L[q0], M[q0]);
         c.first = i;
         c.Lmax = 0;
         c.kmax = 0;
         c.cost = 0;
         int64_t j = i;
-        while (j < nq && M[idx[j]] == c.M && ni_bucket(L[idx[j]]) == c.ni) {
+        while (j < nq && M[idx[j]] == c.M && ni_bucket(L[idx[j]], c.M) == c.ni) {
             c.Lmax = std::max(c.Lmax, L[idx[j]]);
             c.kmax = std::max(c.kmax, k[idx[j]]);
             c.cost += L[idx[j]];

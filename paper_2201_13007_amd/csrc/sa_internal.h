@@ -109,10 +109,12 @@ uint32_t search_lds_bytes(int32_t L, int32_t M, int32_t llog2, int32_t d);
 void search_table_log2(const sa_search_params &p, int32_t L, int32_t M, int32_t R, int32_t *llog2, int32_t *glog2);
 
 // Register-queue slots per lane the search kernels are compiled for: ceil(L / 64)
-// rounded up to 1, 2, 4, 6, 8 or 16.
-inline int queue_slots_bucket(int L)
+// rounded up: for one walker (the single-worker kernel) to 1, 2, ..., 8 or 16, for more
+// (the general kernel) to 1, 2, 4, 6, 8 or 16.
+inline int queue_slots_bucket(int L, int M)
 {
     const int ni = (L + 63) / 64;
+    if (M == 1 && ni <= 8) return ni < 1 ? 1 : ni;
     return ni <= 1 ? 1 : ni <= 2 ? 2 : ni <= 4 ? 4 : ni <= 6 ? 6 : ni <= 8 ? 8 : 16;
 }
 

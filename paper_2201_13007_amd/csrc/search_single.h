@@ -346,8 +346,11 @@ hipError_t launch1_ni(const KArgs &A, int64_t nq, hipStream_t s)
     const int ni = (A.L + 63) / 64;
     if (ni <= 1) return launch1<LPV, 1, DT>(A, nq, s);
     if (ni <= 2) return launch1<LPV, 2, DT>(A, nq, s);
+    if (ni <= 3) return launch1<LPV, 3, DT>(A, nq, s);
     if (ni <= 4) return launch1<LPV, 4, DT>(A, nq, s);
+    if (ni <= 5) return launch1<LPV, 5, DT>(A, nq, s);
     if (ni <= 6) return launch1<LPV, 6, DT>(A, nq, s);
+    if (ni <= 7) return launch1<LPV, 7, DT>(A, nq, s);
     if (ni <= 8) return launch1<LPV, 8, DT>(A, nq, s);
     return launch1<LPV, 16, DT>(A, nq, s);
 }

@@ -73,14 +73,14 @@ struct Slot {
 bool class_less(const Request &a, const Request &c)
 {
     if (a.M != c.M) return a.M < c.M;
-    const int na = queue_slots_bucket(a.L), nc = queue_slots_bucket(c.L);
+    const int na = queue_slots_bucket(a.L, a.M), nc = queue_slots_bucket(c.L, c.M);
     if (na != nc) return na < nc;
     if (a.L != c.L) return a.L > c.L;
     return a.t_submit < c.t_submit;
 }
 bool same_class(const Request &a, const Request &c)
 {
-    return a.M == c.M && queue_slots_bucket(a.L) == queue_slots_bucket(c.L);
+    return a.M == c.M && queue_slots_bucket(a.L, a.M) == queue_slots_bucket(c.L, c.M);
 }
 
 }  // namespace
@@ -120,7 +120,7 @@ size_t out_bytes(const sa_server *S) { return 8 * (size_t)S->cfg.max_batch * S->
 // bytes of workspace a request reserves: the region of its class's largest possible L
 size_t request_region(const sa_server *S, int32_t L, int32_t M)
 {
-    const int Lb = std::min(1024, 64 * queue_slots_bucket(L));
+    const int Lb = std::min(1024, 64 * queue_slots_bucket(L, M));
     return search_workspace_bytes(1, Lb, M, S->p, S->ix->R);
 }
 

@@ -291,6 +291,16 @@ def test_search_sift_shaped(B, sift_setup, L, M):
         assert_search_equal(g, e, exact=True, label=f"sift L={L} M={M} {sync}")
 
 
+@pytest.mark.parametrize("L", [160, 288, 352, 416, 480])
+def test_search_single_queue_sizes(B, sift_setup, L):
+    # one walker: every register-queue size the single-worker kernel is compiled for
+    # between 128 and 512 (3, 5, 6, 7 and 8 slots per lane; 1, 2 and 4 run above)
+    w, adj, entry = sift_setup
+    print(f"case: search sift-20k single worker L={L}", flush=True)
+    g, e = run_both(B, w.base, adj, entry, w.queries, 10, L, 1)
+    assert_search_equal(g, e, exact=True, label=f"sift single L={L}")
+
+
 def test_search_golden_line(B):
     with open(os.path.join(GOLDEN, "line10_adaptive.json")) as f:
         gl = json.load(f)
