@@ -80,6 +80,13 @@ typedef struct {
                                final list get exact distances from the index's float32 vectors
                                and the first k of them by key are returned; -1: the whole final
                                list.  Needs float32 vectors in the index (SA_EINVAL otherwise). */
+    int32_t ws_hash_init;   /* one walker without an LDS table: the visited-set slots a query
+                               starts with, a power of two in [128, ws_hash_slots] with 3/4 of
+                               it above M * R; 0 = the larger of 8192 and 24 L, rounded up,
+                               at most ws_hash_slots.  A query whose set would pass three quarters
+                               of its table moves it into one twice as large (flag
+                               SA_QFLAG_SPILLED), up to ws_hash_slots.  Smaller tables keep more
+                               of the visited sets of the queries in flight in the caches. */
 } sa_search_params;
 
 /* Per-query counters written by sa_search when stats_dev is not NULL. */
@@ -96,7 +103,8 @@ typedef struct {
 
 #define SA_QFLAG_MAX_STEPS 1   /* stopped by max_substeps: result is the global queue then */
 #define SA_QFLAG_CAPACITY 2    /* the workspace visited set filled up: result is partial */
-#define SA_QFLAG_SPILLED 4     /* the visited set moved from LDS to the workspace */
+#define SA_QFLAG_SPILLED 4     /* the visited set outgrew its first table (the LDS table, or
+                                  with one walker the first workspace table) and moved */
 
 typedef struct sa_index sa_index;
 

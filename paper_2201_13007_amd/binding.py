@@ -31,7 +31,7 @@ EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_quan
 class SearchParams(C.Structure):
     _fields_ = [("sync", C.c_int32), ("static_I", C.c_int32), ("rho", C.c_double), ("staged", C.c_int32),
                 ("max_substeps", C.c_int32), ("lds_hash_slots", C.c_int32), ("ws_hash_slots", C.c_int32),
-                ("rerank", C.c_int32)]
+                ("rerank", C.c_int32), ("ws_hash_init", C.c_int32)]
 
 
 class ServerConfig(C.Structure):
@@ -245,7 +245,7 @@ def build_graph(base: torch.Tensor, knn_k: int, R: int, prune_mode="rng", do_rep
 
 
 def make_params(sync="adaptive", static_I=0, rho=0.8, staged=True, max_substeps=0, lds_hash_slots=0,
-                ws_hash_slots=0, rerank=0) -> SearchParams:
+                ws_hash_slots=0, rerank=0, ws_hash_init=0) -> SearchParams:
     p = SearchParams()
     lib().sa_default_params(C.byref(p))
     p.sync = SYNC[sync] if isinstance(sync, str) else int(sync)
@@ -256,6 +256,7 @@ def make_params(sync="adaptive", static_I=0, rho=0.8, staged=True, max_substeps=
     p.lds_hash_slots = int(lds_hash_slots)
     p.ws_hash_slots = int(ws_hash_slots)
     p.rerank = int(rerank)
+    p.ws_hash_init = int(ws_hash_init)
     return p
 
 

@@ -136,6 +136,24 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     A.d = a.d; A.metric = a.metric; A.R = a.R; A.entry = a.entry; A.k = a.k; A.L = a.L; A.M = a.M;
     A.sync = a.p.sync; A.static_I = a.p.static_I; A.staged = a.p.staged ? 1 : 0; A.max_substeps = max_sub;
     A.rho = a.p.rho; A.glog2 = glog2; A.llog2 = llog2;
+    // The single worker starts in a table of at least 8192 and 24 L slots (a search visits
+    // some 7-15 L vertices, so it stays under about 40% full, where the probe chains are
+    // still short) rather than in the whole region: smaller tables keep more of the tables
+    // of the queries in flight in the caches.  A query that outgrows it moves into one
+    // twice as large, up to the region's 2^glog2.
+    if (a.p.ws_hash_init > 0) {
+        const int t = ilog2_exact(a.p.ws_hash_init);
+        if (t < 7 || t > glog2 || (int64_t(1) << t) != a.p.ws_hash_init)
+            return set_error(SA_EINVAL, "ws_hash_init must be a power of two in [128, %d]", 1 << glog2);
+        if ((int64_t(1) << t) * 3 / 4 < (int64_t)a.M * a.R + 1)
+            return set_error(SA_EINVAL, "ws_hash_init too small for M * R new vertices per local step");
+        A.glog2_init = t;
+    } else {
+        const int64_t want0 = std::max<int64_t>(8192, 24ll * a.L);
+        int t = 10;
+        while (t < glog2 && (int64_t(1) << t) < want0) ++t;
+        A.glog2_init = std::min(t, glog2);
+    }
     A.o_skey = Y.o_skey; A.o_srank = Y.o_srank; A.o_schk = Y.o_schk; A.o_pub = Y.o_pub;
     A.o_newkey = Y.o_newkey; A.o_claim = Y.o_claim; A.o_ctrl = Y.o_ctrl;
     A.o_hash = Y.o_hash; A.o_q = Y.o_q;

@@ -77,6 +77,7 @@ struct KArgs {
     int32_t d, metric, R, entry, k, L, M, sync, static_I, staged, max_substeps;
     double rho;
     int32_t glog2, llog2;        // llog2 == 0: no LDS table
+    int32_t glog2_init;          // single worker: log2 of the table a query starts in (<= glog2)
     uint32_t o_skey, o_srank, o_schk, o_pub, o_newkey, o_claim, o_ctrl, o_hash, o_q;
     // batches: per-query L and k (null: L and k above) and the query each workgroup
     // runs (null: workgroup b runs query b)

@@ -168,6 +168,24 @@ __device__ __forceinline__ uint32_t claim(uint32_t *T, int log2cap, uint32_t u, 
     return NO_SLOT;
 }
 
+// Moves the visited set from the table in use into one twice as large, 2^t2 entries at
+// the same address (the region holds the largest): every entry is taken out through the
+// slot list (exchanged for 0) and inserted again, and the slot list then holds the new
+// slots.  The whole wavefront takes part.
+__device__ __forceinline__ void grow_table(uint32_t *tbl, uint32_t *slots, int nslot, int t2)
+{
+    const int lane = __lane_id();
+    for (int i = lane; i < nslot; i += 64) slots[i] = atomicExch(&tbl[slots[i]], 0u);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    for (int i = lane; i < nslot; i += 64) {
+        bool fresh;
+        slots[i] = claim(tbl, t2, slots[i] - 1u, &fresh);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int LPV, int NI, bool L2, int DT>
 __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_t *tbl)
 {
@@ -182,7 +200,10 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
     const int kq = A.qk ? A.qk[qi] : A.k;
     const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
     uint32_t *const slots = tbl + (1u << g2);
-    const int cap = (3 << g2) / 4;
+    // the table in use is the first 2^t2 entries of the region's 2^g2; it doubles when
+    // the visited set would pass three quarters of it
+    int t2 = A.glog2_init;
+    int cap = (3 << t2) / 4;
     const VecSrc V{A.codes, A.scale, A.ldc};
 
     {
@@ -213,7 +234,7 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
         if (lane == 0) Q.k[0] = k0;
         Q.len = 1;
         bool fresh = false;
-        const uint32_t s0 = lane == 0 ? claim(tbl, g2, (uint32_t)A.entry, &fresh) : 0u;
+        const uint32_t s0 = lane == 0 ? claim(tbl, t2, (uint32_t)A.entry, &fresh) : 0u;
         if (lane == 0) slots[0] = s0;
         nslot = 1;
     }
@@ -247,7 +268,7 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             pu = adj_lane[(int64_t)pv * R];
             if (lane >= R || u < 0 || u >= n) u = -1;   // padding and malformed entries
             bool fresh = false;
-            const uint32_t slot = u >= 0 ? claim(tbl, g2, (uint32_t)u, &fresh) : NO_SLOT;
+            const uint32_t slot = u >= 0 ? claim(tbl, t2, (uint32_t)u, &fresh) : NO_SLOT;
             const uint64_t fm = __ballot(fresh);
             const int nnew = __popcll(fm);
             if (fresh) {
@@ -267,9 +288,16 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             const int U = sbits ? insert_batch(Q, L, mk, sbits, nkey) : L;
             cur = first_unchecked(Q);
             if (nslot + R > cap) {
-                flags |= SA_QFLAG_CAPACITY;
-                stop = true;
-                break;
+                if (t2 < g2) {
+                    // (one doubling suffices: nslot <= cap before, and R <= 64 < cap)
+                    grow_table(tbl, slots, nslot, ++t2);
+                    cap = (3 << t2) / 4;
+                    flags |= SA_QFLAG_SPILLED;
+                } else {
+                    flags |= SA_QFLAG_CAPACITY;
+                    stop = true;
+                    break;
+                }
             }
             bool merge_now;
             if (A.sync == SA_SYNC_BSP) merge_now = true;

@@ -301,6 +301,29 @@ def test_search_single_queue_sizes(B, sift_setup, L):
     assert_search_equal(g, e, exact=True, label=f"sift single L={L}")
 
 
+@pytest.mark.parametrize("init", [128, 512, 0])
+def test_search_single_table_growth(B, sift_setup, init):
+    # one walker starting in a small visited table: queries whose set outgrows it move it
+    # into tables twice as large, with results and counters unchanged; the workspace is
+    # left zero-filled for the next launch
+    w, adj, entry = sift_setup
+    print(f"case: search sift-20k single worker L=100 ws_hash_init={init}", flush=True)
+    ix = B.Index(dev(w.base), dev(adj), entry)
+    r = ix.search(dev(w.queries), 10, 100, 1, stats=True, ws_hash_init=init)
+    torch.cuda.synchronize()
+    assert int(ix._ws.count_nonzero().item()) == 0
+    g = (host(r.ids), host(r.dists), host(r.stats))
+    e = oracle.speedann(w.base, adj, entry, w.queries, 10, 100, 1)
+    assert_search_equal(g, e, exact=True, label=f"sift single growth init={init}")
+    grown = (g[2][:, 5] & 4) != 0
+    if init == 128:
+        assert grown.all()
+    elif init == 512:
+        assert grown.any()
+    with pytest.raises(B.SpeedAnnError, match="ws_hash_init"):
+        ix.search(dev(w.queries), 10, 100, 1, ws_hash_init=96)
+
+
 def test_search_golden_line(B):
     with open(os.path.join(GOLDEN, "line10_adaptive.json")) as f:
         gl = json.load(f)
