@@ -81,9 +81,9 @@ typedef struct {
                                and the first k of them by key are returned; -1: the whole final
                                list.  Needs float32 vectors in the index (SA_EINVAL otherwise). */
     int32_t ws_hash_init;   /* one walker without an LDS table: the visited-set slots a query
-                               starts with, a power of two in [128, ws_hash_slots] with 3/4 of
-                               it above M * R; 0 = the larger of 8192 and 24 L, rounded up,
-                               at most ws_hash_slots.  A query whose set would pass three quarters
+                               starts with, a power of two >= 128 with 3/4 of it above R
+                               (ignored for M >= 2); capped at ws_hash_slots; 0 = the larger
+                               of 8192 and 24 L, rounded up.  A query whose set would pass three quarters
                                of its table moves it into one twice as large (flag
                                SA_QFLAG_SPILLED), up to ws_hash_slots.  Smaller tables keep more
                                of the visited sets of the queries in flight in the caches. */

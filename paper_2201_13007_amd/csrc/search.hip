@@ -141,13 +141,14 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     // still short) rather than in the whole region: smaller tables keep more of the tables
     // of the queries in flight in the caches.  A query that outgrows it moves into one
     // twice as large, up to the region's 2^glog2.
-    if (a.p.ws_hash_init > 0) {
+    if (a.p.ws_hash_init > 0 && compact_table(a.M, llog2)) {
+        // (used by one walker only; larger than the region means the region)
         const int t = ilog2_exact(a.p.ws_hash_init);
-        if (t < 7 || t > glog2 || (int64_t(1) << t) != a.p.ws_hash_init)
-            return set_error(SA_EINVAL, "ws_hash_init must be a power of two in [128, %d]", 1 << glog2);
-        if ((int64_t(1) << t) * 3 / 4 < (int64_t)a.M * a.R + 1)
-            return set_error(SA_EINVAL, "ws_hash_init too small for M * R new vertices per local step");
-        A.glog2_init = t;
+        if (t < 7 || (int64_t(1) << t) != a.p.ws_hash_init)
+            return set_error(SA_EINVAL, "ws_hash_init must be a power of two >= 128");
+        if ((int64_t(1) << t) * 3 / 4 < (int64_t)a.R + 1)
+            return set_error(SA_EINVAL, "ws_hash_init too small for R new vertices per local step");
+        A.glog2_init = std::min(t, glog2);
     } else {
         const int64_t want0 = std::max<int64_t>(8192, 24ll * a.L);
         int t = 10;

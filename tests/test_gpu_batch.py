@@ -43,13 +43,17 @@ def gist():
     return w, adj, entry, L, w.info["k"].astype(np.int32), w.info["M"].astype(np.int32)
 
 
-def test_batch_matches_oracle_per_query(B, gist):
+@pytest.mark.parametrize("init", [0, 256])
+def test_batch_matches_oracle_per_query(B, gist, init):
+    # init = 256: the one-walker classes start in a 256-slot visited table and grow it
     w, adj, entry, L, k, M = gist
-    print(f"case: batch gist-4000x960 nq={len(L)} mixed L/k/M", flush=True)
+    print(f"case: batch gist-4000x960 nq={len(L)} mixed L/k/M ws_hash_init={init}", flush=True)
     ix = B.Index(dev(w.base), dev(adj), entry)
-    bt = B.Batch(ix, L, k, M, rho=0.8)
+    bt = B.Batch(ix, L, k, M, rho=0.8, ws_hash_init=init)
     r = bt.run(dev(w.queries), stats=True)
     gids, gd, gst = host(r.ids), host(r.dists), host(r.stats)
+    if init:
+        assert ((gst[M == 1, 5] & 4) != 0).any()
     for q in range(len(L)):
         eids, ed, est = oracle.speedann(w.base, adj, entry, w.queries[q:q + 1], int(k[q]), int(L[q]), int(M[q]),
                                         rho=0.8)

@@ -322,6 +322,10 @@ def test_search_single_table_growth(B, sift_setup, init):
         assert grown.any()
     with pytest.raises(B.SpeedAnnError, match="ws_hash_init"):
         ix.search(dev(w.queries), 10, 100, 1, ws_hash_init=96)
+    # larger than the region: the region; ignored with several walkers
+    r2 = ix.search(dev(w.queries), 10, 100, 1, ws_hash_init=1 << 20)
+    np.testing.assert_array_equal(host(r2.ids), g[0])
+    ix.search(dev(w.queries), 10, 100, 4, ws_hash_init=128)
 
 
 def test_search_golden_line(B):
