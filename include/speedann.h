@@ -82,7 +82,9 @@ typedef struct {
                                list.  Needs float32 vectors in the index (SA_EINVAL otherwise). */
     int32_t ws_hash_init;   /* one walker without an LDS table: the visited-set slots a query
                                starts with, a power of two >= 128 with 3/4 of it above R
-                               (ignored for M >= 2); capped at ws_hash_slots; 0 = the larger
+                               (ignored for M >= 2); capped at ws_hash_slots; 0 = automatic:
+                               ws_hash_slots when the tables of the queries that can be
+                               resident at once fit in 128 MB at that size, else the larger
                                of 8192 and 24 L, rounded up.  A query whose set would pass three quarters
                                of its table moves it into one twice as large (flag
                                SA_QFLAG_SPILLED), up to ws_hash_slots.  Smaller tables keep more

@@ -136,11 +136,14 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     A.d = a.d; A.metric = a.metric; A.R = a.R; A.entry = a.entry; A.k = a.k; A.L = a.L; A.M = a.M;
     A.sync = a.p.sync; A.static_I = a.p.static_I; A.staged = a.p.staged ? 1 : 0; A.max_substeps = max_sub;
     A.rho = a.p.rho; A.glog2 = glog2; A.llog2 = llog2;
-    // The single worker starts in a table of at least 8192 and 24 L slots (a search visits
-    // some 7-15 L vertices, so it stays under about 40% full, where the probe chains are
-    // still short) rather than in the whole region: smaller tables keep more of the tables
-    // of the queries in flight in the caches.  A query that outgrows it moves into one
-    // twice as large, up to the region's 2^glog2.
+    // The single worker starts in the whole region, unless the region-sized tables of the
+    // queries that can be resident at once (at most 256 CUs x 24 wavefronts) would take
+    // more than half of the 256 MB Infinity Cache: then it starts in a table of at least
+    // 8192 and 24 L slots (a search visits some 7-15 L vertices, so it stays under about
+    // 40% full, where probe chains are still short), and the smaller tables keep the
+    // claims out of HBM.  With fewer queries in flight the emptier region-sized table is
+    // faster.  A query that outgrows its table moves into one twice as large, up to the
+    // region's 2^glog2.
     if (a.p.ws_hash_init > 0 && compact_table(a.M, llog2)) {
         // (used by one walker only; larger than the region means the region)
         const int t = ilog2_exact(a.p.ws_hash_init);
@@ -150,10 +153,12 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
             return set_error(SA_EINVAL, "ws_hash_init too small for R new vertices per local step");
         A.glog2_init = std::min(t, glog2);
     } else {
+        const int64_t resident = std::min<int64_t>(a.nq, 256 * 24);
+        const bool crowded = resident * (int64_t(4) << glog2) > (int64_t(128) << 20);
         const int64_t want0 = std::max<int64_t>(8192, 24ll * a.L);
         int t = 10;
         while (t < glog2 && (int64_t(1) << t) < want0) ++t;
-        A.glog2_init = std::min(t, glog2);
+        A.glog2_init = crowded ? std::min(t, glog2) : glog2;
     }
     A.o_skey = Y.o_skey; A.o_srank = Y.o_srank; A.o_schk = Y.o_schk; A.o_pub = Y.o_pub;
     A.o_newkey = Y.o_newkey; A.o_claim = Y.o_claim; A.o_ctrl = Y.o_ctrl;
