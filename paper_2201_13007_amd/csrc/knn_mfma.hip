@@ -299,6 +299,9 @@ __global__ void __launch_bounds__(256) knn_prep_float_kernel(FPrepArgs P)
             v = 0.f;
         }
         if (P.colsum && row < P.n && c < P.d) v -= (float)(P.colsum[c] / P.n_base);
+        // nonzero magnitudes below 2^-60 could give subnormal bf16 parts, which the matrix
+        // cores may flush: such data goes to the scan
+        if (v != 0.f && fabsf(v) < 0x1p-60f) bad = true;
         const uint16_t hb = bf16_rne_bits(v);
         const float hf = __uint_as_float((uint32_t)hb << 16);
         const uint16_t lb = bf16_rne_bits(v - hf);   // v - hf is exact
@@ -511,8 +514,10 @@ __global__ void __launch_bounds__(64) knn_exact_kernel(EArgs E)
         // (for L2 the last term also covers the rounding of the centred coordinates)
         const double c = 3.1 / 65536.0 + (3.0 * E.d + 2.0) / 16777216.0;
         const double nq_ = sqrt((double)E.qn[q]), nm = sqrt((double)__uint_as_float(*E.max_norm2));
-        const double err = E.metric == SA_L2 ? 2.0 * (2.0 * c * nq_ * nm + 8.0 / 16777216.0 * (nq_ + nm) * (nq_ + nm))
-                                             : 2.0 * (c * nq_ * nm + 2.0 / 16777216.0 * nq_ * nm);
+        // (the last term: fp32 products and partial sums below 2^-126 that may be flushed)
+        const double tiny = (3.0 * E.d + 2.0) * 0x1p-126;
+        const double err = E.metric == SA_L2 ? 2.0 * (2.0 * c * nq_ * nm + 8.0 / 16777216.0 * (nq_ + nm) * (nq_ + nm) + 2.0 * tiny)
+                                             : 2.0 * (c * nq_ * nm + 2.0 / 16777216.0 * nq_ * nm + tiny);
         const int kk = E.k - 1;
         const unsigned long long kth = __shfl(kk < 64 ? key[0] : key[1], kk & 63, 64);
         const double Kk = key_dist(kth);

@@ -459,6 +459,22 @@ def test_knn_float_mfma_equals_scan(B, case):
         np.testing.assert_array_equal(host(ids), eids)
 
 
+@pytest.mark.parametrize("scale,path", [(1e-3, "mfma"), (1e-20, "scan")])
+def test_knn_float_tiny_magnitudes(B, scale, path):
+    # magnitudes far below 1 keep the matrix-core path while every bf16 part and product
+    # stays normal; below 2^-60 the call goes to the scan (the matrix cores may flush
+    # subnormals, which the error bound does not cover); the result is the scan's either way
+    w = synth.deep_like(n=3000, nq=20)
+    base = (w.base.astype(np.float64) * scale).astype(np.float32)
+    q = (w.queries.astype(np.float64) * scale).astype(np.float32)
+    print(f"case: knn float magnitudes x{scale:g}", flush=True)
+    ids, d, used = B.knn(dev(base), dev(q), 10, return_path=True)
+    sids, sd = B.knn(dev(base), dev(q), 10, path="scan")
+    assert used == path
+    np.testing.assert_array_equal(host(ids), host(sids))
+    np.testing.assert_array_equal(host(d), host(sd))
+
+
 @pytest.mark.parametrize("self_join", [False, True])
 def test_knn_float_rescan_ties(B, self_join):
     # 300 copies of one row: the queries at that row see more than 128 points tied within
