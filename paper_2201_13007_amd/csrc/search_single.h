@@ -28,6 +28,23 @@ namespace single_detail {
 
 using search_detail::KArgs;
 using search_detail::NO_SLOT;
+
+// log2 of the entries of the per-query LDS filter of recently seen vertices: the largest
+// (up to 1024 entries, 4 KB) that keeps a wavefront's LDS within 160 KB / 28, so that LDS
+// never holds a CU below the 28 wavefronts the registers allow
+template <int LPV>
+constexpr int seen_log2()
+{
+    int l = 10;
+    while (l > 6 && 64 * 8 + 64 * 4 + 64 * LPV + (4 << l) > 160 * 1024 / 28) --l;
+    return l;
+}
+
+template <int LPV>
+constexpr uint32_t single_lds_bytes()
+{
+    return 64 * 8 + 64 * 4 + 64 * LPV + (4u << seen_log2<LPV>());
+}
 using search_detail::VecSrc;
 using search_detail::bpermute64;
 using search_detail::distances;
@@ -193,6 +210,11 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
     uint64_t *const nkey = reinterpret_cast<uint64_t *>(smem);    // [64] keys of new vertices
     int32_t *const sid = reinterpret_cast<int32_t *>(nkey + 64);   // [64] their ids
     float *const qs = reinterpret_cast<float *>(sid + 64);          // [16 LPV] the query
+    // [SEEN] ids + 1 of recently claimed or rejected vertices, direct mapped: a vertex found
+    // here is visited and needs no compare-and-swap in the workspace table
+    uint32_t *const seen = reinterpret_cast<uint32_t *>(qs + 16 * LPV);
+    constexpr int SEEN_LOG2 = seen_log2<LPV>();
+    constexpr int SEEN = 1 << SEEN_LOG2;
 
     const int lane = __lane_id();
     const int R = A.R, g2 = A.glog2;
@@ -213,6 +235,7 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             reinterpret_cast<float4 *>(qs)[c] =
                 c < nch ? *reinterpret_cast<const float4 *>(qrow + 4 * c) : make_float4(0.f, 0.f, 0.f, 0.f);
         if (lane == 0) sid[0] = A.entry;
+        for (int i = lane; i < SEEN; i += 64) seen[i] = 0u;
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -268,7 +291,10 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             pu = adj_lane[(int64_t)pv * R];
             if (lane >= R || u < 0 || u >= n) u = -1;   // padding and malformed entries
             bool fresh = false;
-            const uint32_t slot = u >= 0 ? claim(tbl, t2, (uint32_t)u, &fresh) : NO_SLOT;
+            const uint32_t hs = ((uint32_t)u * 2654435761u) >> (32 - SEEN_LOG2);
+            const bool ask = u >= 0 && seen[hs] != (uint32_t)u + 1u;
+            const uint32_t slot = ask ? claim(tbl, t2, (uint32_t)u, &fresh) : NO_SLOT;
+            if (ask) seen[hs] = (uint32_t)u + 1u;
             const uint64_t fm = __ballot(fresh);
             const int nnew = __popcll(fm);
             if (fresh) {
@@ -363,7 +389,7 @@ template <int LPV, int NI, int DT>
 hipError_t launch1(const KArgs &A, int64_t nq, hipStream_t s)
 {
     auto k = A.metric == SA_L2 ? search_single<LPV, NI, true, DT> : search_single<LPV, NI, false, DT>;
-    const uint32_t lds = 64 * 8 + 64 * 4 + 64 * LPV;
+    const uint32_t lds = single_lds_bytes<LPV>();
     hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64), lds, s, A);
     return hipGetLastError();
 }
