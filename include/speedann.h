@@ -222,6 +222,22 @@ int sa_index_create(const float *vec_dev, int64_t n, int32_t d, int64_t ld, int3
                     const int32_t *adj_dev, int32_t R, int32_t entry, sa_index **out);
 void sa_index_destroy(sa_index *index);
 
+/* Scans an index's float32 storage once (synchronous: waits for hip_stream, then runs on
+ * the null stream).  If every coordinate is an integer in a range [lo, hi] such that
+ * (hi - lo)^2 * d and max(|lo|, |hi|)^2 * d are below 2^24, every partial sum of a squared
+ * distance or inner product between vectors and queries in that range is an integer
+ * below 2^24, exact in float32 in any order of addition.  sa_search with one walker then
+ * accumulates the distances of the queries whose coordinates are all integers in [lo, hi]
+ * in float32 (fewer registers, more queries in flight) and the others in double, in two
+ * launches; every key is the same as without the scan.  Without this call, or for other
+ * storage types, the search accumulates in double.  Returns SA_OK whether or not the data
+ * qualify (sa_index_integer_range tells). */
+int sa_index_analyze(sa_index *index, void *hip_stream);
+
+/* 1 and [*lo, *hi] (either pointer may be NULL) when sa_index_analyze found the index's
+ * vectors integer-valued as described there; 0 otherwise. */
+int32_t sa_index_integer_range(const sa_index *index, int32_t *lo, int32_t *hi);
+
 /* Reduced-precision copy of n vectors (rows of d float32, stride ld, 16-byte aligned):
  *   dtype      SA_BF16 or SA_FP8E4M3
  *   codes_dev  n rows of ldc codes (2 bytes each for bf16, 1 for fp8), ldc >= d,

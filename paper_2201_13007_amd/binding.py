@@ -25,7 +25,7 @@ EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_quan
            "sa_batch_tune", "sa_batch_set_config", "sa_batch_describe", "sa_server_default_config",
            "sa_server_create", "sa_server_destroy", "sa_server_submit", "sa_server_poll", "sa_server_replay",
            "sa_server_stats", "sa_graph_order", "sa_permute_rows", "sa_permute_graph", "sa_index_set_id_map",
-           "sa_gather_probe", "sa_knn_last_rescanned"]
+           "sa_gather_probe", "sa_knn_last_rescanned", "sa_index_analyze", "sa_index_integer_range"]
 
 
 class SearchParams(C.Structure):
@@ -65,6 +65,9 @@ def lib():
         L.sa_knn_ex.argtypes = [vp, i64, i32, i64, vp, i64, i64, i32, i32, i32, vp, vp, i32, C.POINTER(C.c_int32), vp]
         L.sa_knn_last_rescanned.argtypes = []
         L.sa_knn_last_rescanned.restype = i64
+        L.sa_index_analyze.argtypes = [vp, vp]
+        L.sa_index_integer_range.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.sa_index_integer_range.restype = i32
         L.sa_medoid.argtypes = [vp, i64, i32, i64, C.POINTER(C.c_int32), vp]
         L.sa_prune.argtypes = [vp, i64, i32, i64, i32, vp, i32, i32, i32, vp, vp]
         L.sa_reverse_edges.argtypes = [vp, i64, i32, i64, i32, vp, i32, C.POINTER(C.c_int64), vp]
@@ -293,10 +296,12 @@ class Index:
     """A graph index over device arrays (borrowed: keep vec and adj alive)."""
 
     def __init__(self, vec: torch.Tensor, adj: torch.Tensor, entry: int, metric="l2", dtype="f32", codes=None,
-                 scale=None, id_map: torch.Tensor | None = None):
+                 scale=None, id_map: torch.Tensor | None = None, analyze=True):
         """vec: float32 vectors.  dtype "bf16" / "fp8": the search reads codes and scale (from
         quantize(vec, dtype), made here when not given) and vec serves the re-rank.
-        id_map: for a renumbered index (reorder), new id -> original id of the results."""
+        id_map: for a renumbered index (reorder), new id -> original id of the results.
+        analyze (float32 storage): scan the vectors once so that integer-valued data can be
+        searched with float32 accumulation (sa_index_analyze; results unchanged)."""
         vec = pad_dim(_mat(vec, "vectors"))
         if adj.dtype != torch.int32 or not adj.is_cuda or not adj.is_contiguous():
             raise SpeedAnnError("adj must be a contiguous int32 device tensor")
@@ -316,6 +321,8 @@ class Index:
         self._h = h
         self._ws = None
         self._lib = lib()   # kept for __del__, which may run after module teardown
+        if dtype == "f32" and analyze:
+            _check(lib().sa_index_analyze(h, _stream(None)), "sa_index_analyze")
         self.id_map = id_map
         if id_map is not None:
             if id_map.dtype != torch.int32 or not id_map.is_cuda or id_map.numel() != vec.shape[0]:
@@ -328,6 +335,13 @@ class Index:
         if h is not None and h.value and L is not None:
             L.sa_index_destroy(h)
             self._h = None
+
+    @property
+    def integer_range(self):
+        """(lo, hi) when the analysed float32 vectors are integers searched with float32
+        accumulation, else None."""
+        lo, hi = C.c_int32(0), C.c_int32(0)
+        return (lo.value, hi.value) if lib().sa_index_integer_range(self._h, C.byref(lo), C.byref(hi)) else None
 
     def workspace_bytes(self, nq, k, L, M, params: SearchParams) -> int:
         return int(lib().sa_search_workspace_bytes(self._h, nq, k, L, M, C.byref(params)))

@@ -86,6 +86,7 @@ int launch_class(const sa_batch *b, const BatchClass &c, const float *queries, i
     a.vec32 = ix->vec32; a.ld32 = ix->ld32;
     a.n = ix->n; a.d = ix->d; a.metric = ix->metric;
     a.adj = ix->adj; a.R = ix->R; a.entry = ix->entry; a.id_map = ix->id_map;
+    a.int_lo = ix->int_lo; a.int_hi = ix->int_hi;
     a.queries = queries; a.ldq = ldq; a.nq = c.n; a.k = c.kmax; a.L = c.Lmax; a.M = c.M;
     a.p = b->p;
     a.p.lds_hash_slots = c.lds;

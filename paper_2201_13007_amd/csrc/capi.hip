@@ -118,6 +118,27 @@ int sa_knn_ex(const float *base_dev, int64_t n, int32_t d, int64_t ld, const flo
 
 int64_t sa_knn_last_rescanned(void) { return knn_rescanned; }
 
+int sa_index_analyze(sa_index *index, void *hip_stream)
+{
+    if (!index) return set_error(SA_EINVAL, "index is NULL");
+    index->int_lo = 1;
+    index->int_hi = 0;
+    if (index->dtype != SA_F32) return SA_OK;
+    int rc;
+    if ((rc = check_device()) != SA_OK) return rc;
+    SA_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+    return index_integer_range(static_cast<const float *>(index->codes), index->n, index->d, index->ldc, &index->int_lo,
+                               &index->int_hi);
+}
+
+int32_t sa_index_integer_range(const sa_index *index, int32_t *lo, int32_t *hi)
+{
+    if (!index || index->int_lo > index->int_hi) return 0;
+    if (lo) *lo = index->int_lo;
+    if (hi) *hi = index->int_hi;
+    return 1;
+}
+
 int sa_knn(const float *base_dev, int64_t n, int32_t d, int64_t ld, const float *queries_dev, int64_t nq, int64_t ldq,
            int32_t k, int32_t metric, int32_t exclude_self, int32_t *ids_dev, float *dists_dev, void *hip_stream)
 {
@@ -294,6 +315,7 @@ int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64
     a.vec32 = index->vec32; a.ld32 = index->ld32;
     a.n = index->n; a.d = index->d; a.metric = index->metric;
     a.adj = index->adj; a.R = index->R; a.entry = index->entry; a.id_map = index->id_map;
+    a.int_lo = index->int_lo; a.int_hi = index->int_hi;
     a.queries = queries_dev; a.ldq = ldq; a.nq = nq; a.k = k; a.L = L; a.M = M; a.p = p;
     a.ids = ids_dev; a.dists = dists_dev; a.stats = stats_dev; a.workspace = workspace; a.ws_bytes = ws_bytes;
     return launch_search(a, (hipStream_t)hip_stream);

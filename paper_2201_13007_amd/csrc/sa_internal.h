@@ -92,7 +92,17 @@ struct SearchLaunch {
     const int32_t *qL = nullptr, *qk = nullptr, *order = nullptr;
     int64_t ldo = 0;       // row stride of ids and dists (0: k)
     const int32_t *id_map = nullptr;   // result ids go through it (a renumbered index)
+    // float32 vectors that are all integers in [int_lo, int_hi] with every exact partial
+    // sum below 2^24 (int_lo > int_hi: not so); see index_integer_range
+    int32_t int_lo = 1, int_hi = 0;
 };
+
+// Whether every stored float32 coordinate is an integer such that, for d-dimensional
+// vectors and queries in the same range, every partial sum of a squared distance or
+// inner product is an integer below 2^24: then float32 arithmetic in any order is exact
+// and equals the double-precision result.  Sets [*lo, *hi] (lo > hi: not so).
+// Synchronous (null stream).
+int index_integer_range(const float *x, int64_t n, int32_t d, int64_t ld, int32_t *lo, int32_t *hi);
 
 // ids of each job's first k (or qk[q]) results replaced by id_map[id]; enqueued only
 int launch_map_ids(int32_t *ids, int64_t ldo, int64_t njobs, int32_t k, const int32_t *order, const int32_t *qk,
@@ -138,4 +148,5 @@ struct sa_index {
     const int32_t *adj;
     int32_t R, entry;
     const int32_t *id_map = nullptr;   // new id -> original id, for renumbered indexes
+    int32_t int_lo = 1, int_hi = 0;    // index_integer_range of float32 codes
 };

@@ -4,6 +4,8 @@
 #include "search_body.h"
 
 #include <algorithm>
+#include <climits>
+#include <cstdlib>
 
 namespace sa {
 namespace {
@@ -105,6 +107,63 @@ size_t search_workspace_bytes(int64_t nq, int32_t L, int32_t M, const sa_search_
     return (size_t)nq * (bytes_per_slot(M, llog2) << glog2);
 }
 
+namespace {
+
+// flags[0]: some coordinate is not an integer of magnitude <= 2^24; flags[1], flags[2]:
+// smallest and largest coordinate (as integers)
+__global__ void integer_range_kernel(const float *x, int64_t n, int32_t d, int64_t ld, int32_t *flags)
+{
+    bool bad = false;
+    int lo = INT_MAX, hi = INT_MIN;
+    const int64_t total = n * d;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / d;
+        const float v = x[r * ld + (e - r * d)];
+        if (!(fabsf(v) <= 16777216.f) || v != rintf(v)) {
+            bad = true;
+        } else {
+            lo = min(lo, (int)v);
+            hi = max(hi, (int)v);
+        }
+    }
+    if (bad) atomicOr(flags, 1);
+    if (lo <= hi) {
+        atomicMin(flags + 1, lo);
+        atomicMax(flags + 2, hi);
+    }
+}
+
+}  // namespace
+
+int index_integer_range(const float *x, int64_t n, int32_t d, int64_t ld, int32_t *lo, int32_t *hi)
+{
+    *lo = 1;
+    *hi = 0;
+    if (n < 1 || d < 1) return SA_OK;
+    int32_t *flags = nullptr;
+    SA_HIP(hipMalloc(reinterpret_cast<void **>(&flags), 16));
+    const int32_t init[3] = {0, INT_MAX, INT_MIN};
+    int32_t res[3] = {1, 0, 0};
+    hipError_t e = hipMemcpy(flags, init, 12, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        const int64_t blocks = std::min<int64_t>((n * d + 255) / 256, 8192);
+        hipLaunchKernelGGL(integer_range_kernel, dim3((unsigned)blocks), dim3(256), 0, 0, x, n, d, ld, flags);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(res, flags, 12, hipMemcpyDeviceToHost);
+    (void)hipFree(flags);
+    if (e != hipSuccess) return hip_fail(e, "integer range of the vectors");
+    if (res[0] != 0 || res[1] > res[2]) return SA_OK;
+    // squared differences of two coordinates in range and products of two: every partial
+    // sum of d of them stays below 2^24
+    const int64_t span = (int64_t)res[2] - res[1], mag = std::max<int64_t>(std::abs((int64_t)res[1]), std::abs((int64_t)res[2]));
+    if (span * span * d < (int64_t(1) << 24) && mag * mag * d < (int64_t(1) << 24)) {
+        *lo = res[1];
+        *hi = res[2];
+    }
+    return SA_OK;
+}
+
 int launch_search(const SearchLaunch &a, hipStream_t stream)
 {
     int llog2, glog2, max_sub;
@@ -167,10 +226,21 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     if (a.d > 1024) return set_error(SA_EUNSUPPORTED, "d=%d exceeds 1024", a.d);
     int rc;
     const bool compact = compact_table(a.M, llog2);
+    A.int_lo = a.int_lo; A.int_hi = a.int_hi; A.acc_pass = -1;
     if (compact) {
         if (a.dtype == SA_BF16) rc = launch_search_single_bf16(A, a.nq, stream);
         else if (a.dtype == SA_FP8E4M3) rc = launch_search_single_fp8(A, a.nq, stream);
-        else rc = launch_search_single_f32(A, a.nq, stream);
+        else if (a.int_lo <= a.int_hi && search_detail::lanes_per_vector(a.d) <= 16) {
+            // integer-valued data: the queries that are integers in the same range in
+            // float32 (exact), the others in double; each workgroup checks its query and
+            // leaves it to the other pass if it is not its own
+            A.acc_pass = 1;
+            rc = launch_search_single_f32(A, a.nq, stream);
+            A.acc_pass = 0;
+            if (rc == SA_OK) rc = launch_search_single_f32(A, a.nq, stream);
+        } else {
+            rc = launch_search_single_f32(A, a.nq, stream);
+        }
     } else {
         if (a.dtype == SA_BF16) rc = launch_search_multi_bf16(A, a.nq, a.M, Y.total, stream);
         else if (a.dtype == SA_FP8E4M3) rc = launch_search_multi_fp8(A, a.nq, a.M, Y.total, stream);

@@ -34,6 +34,8 @@
 #pragma once
 #include "sa_internal.h"
 
+#include <type_traits>
+
 namespace sa {
 namespace search_detail {
 
@@ -78,6 +80,10 @@ struct KArgs {
     double rho;
     int32_t glog2, llog2;        // llog2 == 0: no LDS table
     int32_t glog2_init;          // single worker: log2 of the table a query starts in (<= glog2)
+    // single worker over integer-valued float32 vectors in [int_lo, int_hi] (see
+    // index_integer_range): pass 1 takes the queries that are integers in that range and
+    // accumulates in float32, pass 0 takes the others; -1: one pass takes every query
+    int32_t int_lo, int_hi, acc_pass;
     uint32_t o_skey, o_srank, o_schk, o_pub, o_newkey, o_claim, o_ctrl, o_hash, o_q;
     // batches: per-query L and k (null: L and k above) and the query each workgroup
     // runs (null: workgroup b runs query b)
@@ -174,6 +180,19 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
+// the same sums in float32
+template <int LPV>
+__device__ __forceinline__ float group_sum_f32(float v)
+{
+    if constexpr (LPV >= 2) v += __uint_as_float(dpp32<DPP_ROW_SHR + 1>(__float_as_uint(v), 0u));
+    if constexpr (LPV >= 4) v += __uint_as_float(dpp32<DPP_ROW_SHR + 2>(__float_as_uint(v), 0u));
+    if constexpr (LPV >= 8) v += __uint_as_float(dpp32<DPP_ROW_SHR + 4>(__float_as_uint(v), 0u));
+    if constexpr (LPV >= 16) v += __uint_as_float(dpp32<DPP_ROW_SHR + 8>(__float_as_uint(v), 0u));
+    if constexpr (LPV >= 32) v += __uint_as_float(dpp32<DPP_ROW_BCAST15, 0xA>(__float_as_uint(v), 0u));
+    if constexpr (LPV >= 64) v += __uint_as_float(dpp32<DPP_ROW_BCAST31, 0xC>(__float_as_uint(v), 0u));
+    return v;
+}
+
 // bits [0, n) set, n in [0, 64]
 __device__ __forceinline__ uint64_t low_bits(int n)
 {
@@ -227,7 +246,9 @@ __device__ __forceinline__ Raw4<DT> load_raw4(const VecSrc &V, int32_t id, int c
 // clamped addresses (a dropped id reads row 0): loads under lane conditions each get their
 // own wait, which would turn one memory round trip into four.  (Written as a pass loop
 // over arrays: the same steps as a per-vector helper cost some twenty more registers.)
-template <int LPV, bool L2, int DT>
+// ACC32: accumulate in float32 (only where every partial sum is an integer below 2^24, so
+// that the float32 sum is exact and equals the double one)
+template <int LPV, bool L2, int DT, bool ACC32 = false>
 __device__ __forceinline__ void distances(const VecSrc &V, int d, const float *qs, const int32_t *ids, int n,
                                           uint64_t *out)
 {
@@ -254,7 +275,8 @@ __device__ __forceinline__ void distances(const VecSrc &V, int d, const float *q
         }
 #pragma unroll
         for (int pp = 0; pp < PB; ++pp) {
-            double acc = 0.0;
+            using Acc = typename std::conditional<ACC32, float, double>::type;
+            Acc acc = 0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const bool in = g + LPV * i < nch;
@@ -289,15 +311,16 @@ __device__ __forceinline__ void distances(const VecSrc &V, int d, const float *q
                     bw = s * (float)__builtin_bit_cast(_Float16, (uint16_t)h3);
                 }
                 if constexpr (L2) {
-                    const double t0 = (double)a.x - (double)bx, t1 = (double)a.y - (double)by;
-                    const double t2 = (double)a.z - (double)bz, t3 = (double)a.w - (double)bw;
+                    const Acc t0 = (Acc)a.x - (Acc)bx, t1 = (Acc)a.y - (Acc)by;
+                    const Acc t2 = (Acc)a.z - (Acc)bz, t3 = (Acc)a.w - (Acc)bw;
                     acc += t0 * t0; acc += t1 * t1; acc += t2 * t2; acc += t3 * t3;
                 } else {
-                    acc += (double)a.x * (double)bx; acc += (double)a.y * (double)by;
-                    acc += (double)a.z * (double)bz; acc += (double)a.w * (double)bw;
+                    acc += (Acc)a.x * (Acc)bx; acc += (Acc)a.y * (Acc)by;
+                    acc += (Acc)a.z * (Acc)bz; acc += (Acc)a.w * (Acc)bw;
                 }
             }
-            acc = group_sum<LPV>(acc);
+            if constexpr (ACC32) acc = group_sum_f32<LPV>(acc);
+            else acc = group_sum<LPV>(acc);
             const int idx = p0 + pp * VPW + grp;
             if (g == LPV - 1 && idx < n) out[idx] = make_key(L2 ? (float)acc : (float)(-acc), id[pp]);
         }

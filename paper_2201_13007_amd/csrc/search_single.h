@@ -203,7 +203,7 @@ __device__ __forceinline__ void grow_table(uint32_t *tbl, uint32_t *slots, int n
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int LPV, int NI, bool L2, int DT>
+template <int LPV, int NI, bool L2, int DT, bool ACC32>
 __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_t *tbl)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -231,9 +231,17 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
     {
         const int nch = A.d >> 2;
         const float *qrow = A.queries + qi * A.ldq;
-        for (int c = lane; c < 4 * LPV; c += 64)
-            reinterpret_cast<float4 *>(qs)[c] =
-                c < nch ? *reinterpret_cast<const float4 *>(qrow + 4 * c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float lo = (float)A.int_lo, hi = (float)A.int_hi;
+        bool outside = false;   // some coordinate is not an integer in [int_lo, int_hi]
+        for (int c = lane; c < 4 * LPV; c += 64) {
+            const float4 v = c < nch ? *reinterpret_cast<const float4 *>(qrow + 4 * c) : make_float4(0.f, 0.f, 0.f, 0.f);
+            reinterpret_cast<float4 *>(qs)[c] = v;
+            if (c < nch)
+                outside |= !(v.x == rintf(v.x) && v.x >= lo && v.x <= hi) || !(v.y == rintf(v.y) && v.y >= lo && v.y <= hi) ||
+                           !(v.z == rintf(v.z) && v.z >= lo && v.z <= hi) || !(v.w == rintf(v.w) && v.w >= lo && v.w <= hi);
+        }
+        // with two passes, each query is searched by exactly one of them
+        if (A.acc_pass >= 0 && (__ballot(outside) == 0ull) != (A.acc_pass == 1)) return;
         if (lane == 0) sid[0] = A.entry;
         for (int i = lane; i < SEEN; i += 64) seen[i] = 0u;
     }
@@ -250,7 +258,7 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
         Q.chk[i] = 0;
     }
     // dist(P, Q); P goes into the queue and the visited set
-    distances<LPV, L2, DT>(V, A.d, qs, sid, 1, nkey);
+    distances<LPV, L2, DT, ACC32>(V, A.d, qs, sid, 1, nkey);
     __builtin_amdgcn_wave_barrier();
     {
         const uint64_t k0 = nkey[0];
@@ -304,7 +312,7 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             }
             nslot += nnew;
             __builtin_amdgcn_wave_barrier();
-            distances<LPV, L2, DT>(V, A.d, qs, sid, nnew, nkey);
+            distances<LPV, L2, DT, ACC32>(V, A.d, qs, sid, nnew, nkey);
             __builtin_amdgcn_wave_barrier();
             const uint64_t mk = lane < nnew ? nkey[lane] : KEY_EMPTY;
             __builtin_amdgcn_wave_barrier();
@@ -377,51 +385,61 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
 // longest first is scheduled longest first.  (A persistent loop over jobs in one
 // workgroup was measured: any loop around the search costs 17-36 more VGPRs, about a
 // third of the occupancy this latency-bound search lives on.)
-template <int LPV, int NI, bool L2, int DT>
+template <int LPV, int NI, bool L2, int DT, bool ACC32>
 __global__ void __launch_bounds__(64) search_single(KArgs A)
 {
     const int32_t job = blockIdx.x;
     uint32_t *const tbl = reinterpret_cast<uint32_t *>(A.ghash) + ((size_t)job << (A.glog2 + 1));
-    single_query<LPV, NI, L2, DT>(A, A.order ? A.order[job] : job, tbl);
+    single_query<LPV, NI, L2, DT, ACC32>(A, A.order ? A.order[job] : job, tbl);
 }
 
-template <int LPV, int NI, int DT>
+template <int LPV, int NI, int DT, bool ACC32>
 hipError_t launch1(const KArgs &A, int64_t nq, hipStream_t s)
 {
-    auto k = A.metric == SA_L2 ? search_single<LPV, NI, true, DT> : search_single<LPV, NI, false, DT>;
+    auto k = A.metric == SA_L2 ? search_single<LPV, NI, true, DT, ACC32> : search_single<LPV, NI, false, DT, ACC32>;
     const uint32_t lds = single_lds_bytes<LPV>();
     hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64), lds, s, A);
     return hipGetLastError();
 }
 
-template <int LPV, int DT>
+template <int LPV, int DT, bool ACC32>
 hipError_t launch1_ni(const KArgs &A, int64_t nq, hipStream_t s)
 {
     const int ni = (A.L + 63) / 64;
-    if (ni <= 1) return launch1<LPV, 1, DT>(A, nq, s);
-    if (ni <= 2) return launch1<LPV, 2, DT>(A, nq, s);
-    if (ni <= 3) return launch1<LPV, 3, DT>(A, nq, s);
-    if (ni <= 4) return launch1<LPV, 4, DT>(A, nq, s);
-    if (ni <= 5) return launch1<LPV, 5, DT>(A, nq, s);
-    if (ni <= 6) return launch1<LPV, 6, DT>(A, nq, s);
-    if (ni <= 7) return launch1<LPV, 7, DT>(A, nq, s);
-    if (ni <= 8) return launch1<LPV, 8, DT>(A, nq, s);
-    return launch1<LPV, 16, DT>(A, nq, s);
+    if (ni <= 1) return launch1<LPV, 1, DT, ACC32>(A, nq, s);
+    if (ni <= 2) return launch1<LPV, 2, DT, ACC32>(A, nq, s);
+    if (ni <= 3) return launch1<LPV, 3, DT, ACC32>(A, nq, s);
+    if (ni <= 4) return launch1<LPV, 4, DT, ACC32>(A, nq, s);
+    if (ni <= 5) return launch1<LPV, 5, DT, ACC32>(A, nq, s);
+    if (ni <= 6) return launch1<LPV, 6, DT, ACC32>(A, nq, s);
+    if (ni <= 7) return launch1<LPV, 7, DT, ACC32>(A, nq, s);
+    if (ni <= 8) return launch1<LPV, 8, DT, ACC32>(A, nq, s);
+    return launch1<LPV, 16, DT, ACC32>(A, nq, s);
 }
 
 // one instantiation per storage type, each in a file of its own (search_single_*.hip)
+// float32 accumulation is compiled for float32 storage up to d = 256 (integer data such
+// as 8-bit descriptors); the launcher asks for it only there
+template <int LPV, int DT>
+hipError_t launch_lpv(const KArgs &A, int64_t nq, hipStream_t s)
+{
+    if constexpr (DT == SA_F32 && LPV <= 16)
+        if (A.acc_pass == 1) return launch1_ni<LPV, DT, true>(A, nq, s);
+    return launch1_ni<LPV, DT, false>(A, nq, s);
+}
+
 template <int DT>
 int launch_dt(const KArgs &A, int64_t nq, hipStream_t s)
 {
     hipError_t e;
     switch (search_detail::lanes_per_vector(A.d)) {
-    case 1: e = launch1_ni<1, DT>(A, nq, s); break;
-    case 2: e = launch1_ni<2, DT>(A, nq, s); break;
-    case 4: e = launch1_ni<4, DT>(A, nq, s); break;
-    case 8: e = launch1_ni<8, DT>(A, nq, s); break;
-    case 16: e = launch1_ni<16, DT>(A, nq, s); break;
-    case 32: e = launch1_ni<32, DT>(A, nq, s); break;
-    default: e = launch1_ni<64, DT>(A, nq, s); break;
+    case 1: e = launch_lpv<1, DT>(A, nq, s); break;
+    case 2: e = launch_lpv<2, DT>(A, nq, s); break;
+    case 4: e = launch_lpv<4, DT>(A, nq, s); break;
+    case 8: e = launch_lpv<8, DT>(A, nq, s); break;
+    case 16: e = launch_lpv<16, DT>(A, nq, s); break;
+    case 32: e = launch_lpv<32, DT>(A, nq, s); break;
+    default: e = launch_lpv<64, DT>(A, nq, s); break;
     }
     if (e != hipSuccess) return hip_fail(e, "search kernel launch");
     return SA_OK;

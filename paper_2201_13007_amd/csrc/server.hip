@@ -171,6 +171,7 @@ int launch_slot(sa_server *S, Slot &sl)
         a.vec32 = ix->vec32; a.ld32 = ix->ld32;
         a.n = ix->n; a.d = ix->d; a.metric = ix->metric;
         a.adj = ix->adj; a.R = ix->R; a.entry = ix->entry; a.id_map = ix->id_map;
+        a.int_lo = ix->int_lo; a.int_hi = ix->int_hi;
         // the class's rows: query q of the launch is staged row i + q
         a.queries = reinterpret_cast<const float *>(sl.d_in) + (size_t)i * d; a.ldq = d;
         a.nq = j - i; a.k = kc; a.L = r0.L; a.M = r0.M; a.p = S->p;

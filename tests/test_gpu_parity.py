@@ -328,6 +328,31 @@ def test_search_single_table_growth(B, sift_setup, init):
     ix.search(dev(w.queries), 10, 100, 4, ws_hash_init=128)
 
 
+def test_search_integer_data_two_passes(B, sift_setup):
+    # integer data: queries that are integers in the vectors' range are searched with
+    # float32 accumulation, the others (half-integers, integers outside the range) in
+    # double; every query must give the oracle's result and counters either way
+    w, adj, entry = sift_setup
+    ix = B.Index(dev(w.base), dev(adj), entry)
+    lo, hi = ix.integer_range
+    assert lo == int(w.base.min()) and hi == int(w.base.max())
+    q = w.queries.copy()
+    q[::3, :5] += np.float32(0.5)
+    q[1::7, 7] = np.float32(hi + 40)
+    for L in (64, 288):
+        print(f"case: search sift-20k integer data, mixed queries, L={L}", flush=True)
+        r = ix.search(dev(q), 10, L, 1, stats=True)
+        torch.cuda.synchronize()
+        assert int(ix._ws.count_nonzero().item()) == 0
+        g = (host(r.ids), host(r.dists), host(r.stats))
+        e = oracle.speedann(w.base, adj, entry, q, 10, L, 1)
+        assert_search_equal(g, e, exact=True, label=f"integer data mixed queries L={L}")
+    fx = B.Index(dev(w.base + np.float32(0.25)), dev(adj), entry)
+    assert fx.integer_range is None
+    wide = B.Index(dev(w.base * np.float32(4)), dev(adj), entry)   # span 1020: partial sums reach 2^24
+    assert wide.integer_range is None
+
+
 def test_search_golden_line(B):
     with open(os.path.join(GOLDEN, "line10_adaptive.json")) as f:
         gl = json.load(f)
