@@ -689,6 +689,8 @@ def main():
         base, adj, entry, perm = B.reorder(base, adj, entry, args.order)
         log(f"renumbered ({args.order} order) in {time.time() - t0:.1f}s")
     ix = B.Index(base, adj, entry, metric=w.metric, id_map=perm)
+    int_range = ix.integer_range
+    log(f"integer range of the vectors: {int_range}")
     params = {}
 
     def run(M, L, stats=False, q=queries, out=None):
@@ -840,10 +842,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if int_range else "f64",
         "data": "synthetic",
         "config": {
             "workload": f"sift-like {args.n}x{d} (256-component mixture, sigma 20, 0..255), {args.nq} queries, k={k}",
+            "accumulation": (f"float32, exact: the vectors and queries are integers in {list(int_range)}, so every partial "
+                             f"sum is an integer below 2^24" if int_range else "double, rounded once to float32"),
             "graph": f"exact 64-NN, relative-neighbourhood prune to R={R}, repair (keep_local 1), medoid entry",
             "graph_build_s": round(t_graph, 1),
             "vertex_order": args.order,
