@@ -57,6 +57,11 @@ def test_validation_errors_without_device(B):
     assert L.sa_index_create(fake, 100, 32, 32, 7, fake, 16, 0, C.byref(out)) == -1
     assert L.sa_index_create(fake, 100, 32, 32, 0, fake, 16, 5, C.byref(out)) == 0
     ix = out
+    # not analysed: no integer range, so the search accumulates in double
+    lo, hi = C.c_int32(0), C.c_int32(0)
+    assert L.sa_index_integer_range(ix, C.byref(lo), C.byref(hi)) == 0
+    assert L.sa_index_integer_range(None, None, None) == 0
+    assert L.sa_index_analyze(None, None) == -1 and "NULL" in _err(B)
     p = B.SearchParams()
     L.sa_default_params(C.byref(p))
     # k > L, M > 16, L > 1024
