@@ -107,6 +107,24 @@ def test_rerank(B, deep, dtype, M, rr):
     assert int(ix._ws.count_nonzero().item()) == 0
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_rerank_after_table_growth(B, deep, dtype):
+    # one walker starting in a 128-slot visited table grows it several times; the re-rank
+    # list at the end of the slot list must come through unchanged
+    w, adj, entry = deep
+    L = 64
+    searched = w.base if dtype == "f32" else oracle.dequantize(*oracle.quantize(w.base, dtype), dtype)
+    print(f"case: re-rank {dtype} after visited-table growth", flush=True)
+    ix = B.Index(dev(w.base), dev(adj), entry, metric="ip", dtype=dtype)
+    r = ix.search(dev(w.queries), 10, L, 1, rho=0.9, rerank=-1, ws_hash_init=128, stats=True)
+    assert ((host(r.stats)[:, 5] & 4) != 0).all()
+    final, _, _ = oracle.speedann(searched, adj, entry, w.queries, L, L, 1, rho=0.9, metric="ip")
+    eids, ed = oracle.rerank(w.base, w.queries, final, 10, metric="ip")
+    np.testing.assert_array_equal(host(r.ids), eids)
+    np.testing.assert_allclose(host(r.dists), ed, rtol=1e-5, atol=1e-6)
+    assert int(ix._ws.count_nonzero().item()) == 0
+
+
 def test_rerank_needs_room_and_vectors(B, deep):
     w, adj, entry = deep
     ix = B.Index(dev(w.base), dev(adj), entry, metric="ip", dtype="fp8")
