@@ -72,7 +72,8 @@ void resolve_params(const sa_search_params &in, int L, int M, int R, int &llog2,
     if (in.ws_hash_slots > 0) glog2 = ilog2_exact(in.ws_hash_slots);
     else {
         // the visited set holds at most 1 + E * R vertices after E expansions, and E stays
-        // close to L.  The single-worker table (4-byte entries) takes 32 L slots: its
+        // close to L.  The single-worker region (4-byte entries; a search may start in a
+        // prefix of it, see glog2_init below) takes 32 L slots: its
         // three-quarter limit sits near 24 L, several times the 8 L or so a search visits
         // at these R; the general table keeps 64 L.  8 M R more cover the M R vertices one
         // local step may add on top.

@@ -12,8 +12,9 @@
 // of cross-lane permutes.  No memory round trip.
 //
 // Distances: LPV lanes share one vector, each lane four float4 chunks, accumulated in
-// double precision, summed by DPP row shifts and rounded once to float; the query sits
-// in LDS for all workers.  Every gather and row load is issued unconditionally (from a
+// double precision (the single-worker kernel can also accumulate exact integer data in
+// float32), summed by DPP row shifts and rounded once to float; the query sits in LDS for
+// all workers.  Every gather and row load is issued unconditionally (from a
 // clamped address): loads under lane conditions each get their own wait.
 //
 // Global steps with one active worker (every step when M = 1; the first step of a

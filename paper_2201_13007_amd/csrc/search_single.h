@@ -14,12 +14,16 @@
 // many of them land below it and pulls its old entry with a cross-lane permute.
 //
 // Visited set.  Open addressing over 32-bit entries (id + 1; zero is empty) in the
-// query's workspace region, claimed with compare-and-swap.  The slots a query fills are
-// listed after the table and zeroed again before it ends.
+// query's workspace region, claimed with compare-and-swap.  The table in use is a prefix
+// of the region that doubles (rehashing the set) when it passes three quarters full.  An
+// LDS array of recently claimed or rejected ids sits in front of it: a neighbour found
+// there is visited and needs no compare-and-swap.  The slots a query fills are listed
+// after the table and zeroed again before it ends.
 //
 // Distances.  LPV lanes share one vector, each lane four float4 chunks (c = g, g + LPV,
-// ...), accumulated in double precision, summed into the group's last lane by DPP row
-// shifts and broadcasts, and rounded once to float.  The query row sits in LDS.
+// ...), accumulated in double precision (in float32 where the data and the query are
+// integers that make every partial sum exact), summed into the group's last lane by DPP
+// row shifts and broadcasts, and rounded once to float.  The query row sits in LDS.
 #pragma once
 #include "search_body.h"
 
