@@ -272,7 +272,9 @@ size_t sa_search_workspace_bytes(const sa_index *index, int64_t nq, int32_t k, i
  *                zero-filled before its first use.  Every call leaves it zero-filled again
  *                when it completes, so one buffer serves any number of calls; calls that
  *                share a workspace must not overlap.
- * Allocates nothing.  Enqueued on hip_stream. */
+ * Allocates nothing.  Enqueued on hip_stream: kernel launches only (two of the search
+ * kernel when sa_index_analyze found integer data, then a re-rank and an id-map kernel
+ * when asked for), so the call can be captured in a HIP graph. */
 int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64_t ldq, int32_t k, int32_t L,
               int32_t M, const sa_search_params *params, int32_t *ids_dev, float *dists_dev,
               sa_query_stats *stats_dev, void *workspace, size_t ws_bytes, void *hip_stream);
