@@ -52,6 +52,11 @@ sys.path.insert(0, ROOT)
 if "--workload" in sys.argv and ("serve" in sys.argv or "gist" in sys.argv):
     os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
+# the synchronisation schedules of the paper the latency candidates use (Sec. 4.3)
+SYNCS = {"adaptive": dict(sync="adaptive", rho=0.8, staged=True),
+         "bsp": dict(sync="bsp", staged=True),
+         "static8": dict(sync="static", static_I=8, staged=True)}
+
 L_SWEEP = [32, 48, 64, 80, 96, 112, 128, 144, 160, 176, 192, 208, 224, 240, 256, 272, 288, 304, 320, 336, 352, 384,
            416, 448, 480, 512]
 M_SWEEP = [1, 2, 4, 8, 16]
@@ -98,8 +103,8 @@ def load_traffic(workload_key):
 
 def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors", lockstep=None):
     """The oracle's search timed on the host cores over a growing prefix of the queries
-    until about `seconds` of CPU work.  lockstep=(M2, L2): also the one-thread latency of
-    the oracle at that point (Algorithm 3 with M2 workers, emulated in sequence)."""
+    until about `seconds` of CPU work.  lockstep=(M2, L2, sync keywords): also the one-thread
+    latency of the oracle at that point (Algorithm 3 with M2 workers, emulated in sequence)."""
     import oracle
     adj_h = adj.cpu().numpy()
     nq = w.queries.shape[0]
@@ -133,15 +138,14 @@ def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors", lockstep=
            "latency_p50_ms": round(float(np.percentile(lat, 50)), 4),
            "latency_p99_ms": round(float(np.percentile(lat, 99)), 4),
            "latency_sample": f"first {len(lat)} queries one at a time, one thread, host wall time"}
-    if lockstep is not None and tuple(lockstep) != (M, L):
-        M2, L2 = lockstep
+    if lockstep is not None and tuple(lockstep[:2]) != (M, L):
+        M2, L2, skw = lockstep
         lat2 = []
         for i in range(min(50, nq)):
             s0 = time.perf_counter()
-            oracle.speedann(w.base, adj_h, entry, w.queries[i:i + 1], k, L2, M2, sync="adaptive", rho=0.8,
-                            staged=True, metric=w.metric)
+            oracle.speedann(w.base, adj_h, entry, w.queries[i:i + 1], k, L2, M2, metric=w.metric, **skw)
             lat2.append((time.perf_counter() - s0) * 1e3)
-        cpu["lockstep_point"] = {"M": int(M2), "L": int(L2), "queries": len(lat2),
+        cpu["lockstep_point"] = {"M": int(M2), "L": int(L2), "sync": skw, "queries": len(lat2),
                                  "latency_p50_ms": round(float(np.percentile(lat2, 50)), 4),
                                  "latency_p99_ms": round(float(np.percentile(lat2, 99)), 4)}
     log(f"cpu oracle: {cpu['value']} q/s on {nthreads} threads ({done} queries, {t_cpu:.1f}s)")
@@ -693,9 +697,10 @@ def main():
     log(f"integer range of the vectors: {int_range}")
     params = {}
 
-    def run(M, L, stats=False, q=queries, out=None):
-        p = B.make_params(sync="adaptive", rho=0.8, staged=True)
-        params[(M, L)] = p
+    def run(M, L, stats=False, q=queries, out=None, sync="adaptive"):
+        p = params.get((M, L, sync))
+        if p is None:
+            p = params[(M, L, sync)] = B.make_params(**SYNCS[sync])
         return ix.search(q, k, L, M, params=p, stats=stats, out=out)
 
     def time_launches(M, L, reps):
@@ -784,31 +789,49 @@ def main():
     one = (torch.empty((1, k), dtype=torch.int32, device=dev), torch.empty((1, k), dtype=torch.float32, device=dev),
            None)
 
-    def batch1(Mx, Lx, count):
+    def batch1(Mx, Lx, count, sync="adaptive"):
         for i in range(min(20, count)):
-            run(Mx, Lx, q=queries[i:i + 1], out=one)
+            run(Mx, Lx, q=queries[i:i + 1], out=one, sync=sync)
         torch.cuda.synchronize()
         lat = []
         for i in range(count):
             q1 = queries[i:i + 1]
             s0 = time.perf_counter()
-            run(Mx, Lx, q=q1, out=one)
+            run(Mx, Lx, q=q1, out=one, sync=sync)
             torch.cuda.synchronize()
             lat.append((time.perf_counter() - s0) * 1e3)
         return np.array(lat) if lat else np.array([float("nan")])
 
-    ops = {s["M"]: s["L"] for s in sweep if s["recall"] >= TARGET} if reached else {M: L}
+    # candidates: every M at its adaptive operating point, and for the latency widths
+    # M = 8, 16 the other schedules of the paper at their own smallest L reaching the target
+    # (merging after every local step is Top-M; within one workgroup a merge is cheap)
+    ops = {(s["M"], "adaptive"): s["L"] for s in sweep if s["recall"] >= TARGET} if reached else {(M, "adaptive"): L}
+    op_recall = {(s["M"], "adaptive"): s["recall"] for s in sweep if s["recall"] >= TARGET}
+    if reached and nl > 0 and not args.M:
+        for Mx in (8, 16):
+            for sync in ("bsp", "static8"):
+                for Lx in L_SWEEP:
+                    rec = recall_at_k(run(Mx, Lx, sync=sync).ids, gt, k).mean().item()
+                    if rec >= TARGET:
+                        ops[(Mx, sync)] = Lx
+                        op_recall[(Mx, sync)] = round(rec, 5)
+                        log(f"operating point M={Mx} {sync}: L={Lx} recall {rec:.4f}")
+                        break
     lat_by_M = {}
     if nl > 0:
-        for Mx, Lx in sorted(ops.items()):
-            a = batch1(Mx, Lx, min(300, nl))
-            lat_by_M[Mx] = {"L": Lx, "p50_ms": round(float(np.percentile(a, 50)), 4),
-                            "p99_ms": round(float(np.percentile(a, 99)), 4), "queries": len(a)}
-            log(f"batch-1 latency sample M={Mx} L={Lx}: p50 {lat_by_M[Mx]['p50_ms']:.3f} ms")
-    Mlat = min(lat_by_M, key=lambda m: lat_by_M[m]["p50_ms"]) if lat_by_M else M
-    Llat = ops.get(Mlat, L)
-    lat = batch1(Mlat, Llat, nl)
-    log(f"batch-1 latency M={Mlat} L={Llat}: p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
+        for (Mx, sync), Lx in sorted(ops.items()):
+            a = batch1(Mx, Lx, min(300, nl), sync)
+            key = str(Mx) if sync == "adaptive" else f"{Mx}-{sync}"
+            lat_by_M[key] = {"M": Mx, "sync": sync, "L": Lx, "recall@10": op_recall.get((Mx, sync)),
+                             "p50_ms": round(float(np.percentile(a, 50)), 4),
+                             "p99_ms": round(float(np.percentile(a, 99)), 4), "queries": len(a)}
+            log(f"batch-1 latency sample M={Mx} {sync} L={Lx}: p50 {lat_by_M[key]['p50_ms']:.3f} ms")
+    best_key = min(lat_by_M, key=lambda c: lat_by_M[c]["p50_ms"]) if lat_by_M else None
+    Mlat, sync_lat = (lat_by_M[best_key]["M"], lat_by_M[best_key]["sync"]) if best_key else (M, "adaptive")
+    Llat = ops.get((Mlat, sync_lat), L)
+    lat = batch1(Mlat, Llat, nl, sync_lat)
+    log(f"batch-1 latency M={Mlat} {sync_lat} L={Llat}: p50 {np.percentile(lat, 50):.3f} ms, "
+        f"p99 {np.percentile(lat, 99):.3f} ms")
 
     # ---------------------------------------------------------------- roofline
     d, R = w.base.shape[1], w.graph_R
@@ -829,7 +852,8 @@ def main():
                 "frac_of_gather_ceiling": round(achieved / gc["GBs"], 4)}
 
     # ---------------------------------------------------------------- CPU oracle baseline
-    cpu = None if args.no_cpu else cpu_oracle(w, adj0, entry0, k, L, M, args.cpu_seconds, lockstep=(Mlat, Llat))
+    cpu = None if args.no_cpu else cpu_oracle(w, adj0, entry0, k, L, M, args.cpu_seconds,
+                                              lockstep=(Mlat, Llat, SYNCS[sync_lat]))
 
     res = {
         "metric": "QPS and p50/p99 latency at recall@10=0.99, 1M×128 SIFT-shaped, 1 GPU",
@@ -856,7 +880,8 @@ def main():
             "storage": "f32 vectors, int32 adjacency",
             "p50_ms_batch1": round(float(np.percentile(lat, 50)), 4),
             "p99_ms_batch1": round(float(np.percentile(lat, 99)), 4),
-            "batch1_point": {"M": Mlat, "L": Llat, "queries": nl},
+            "batch1_point": {"M": Mlat, "L": Llat, "sync": sync_lat, "recall@10": op_recall.get((Mlat, sync_lat)),
+                             "queries": nl},
             "batch1_by_M": {str(m): v for m, v in sorted(lat_by_M.items())},
             "p50_ms_in_batch": round(float(np.percentile(svc_ms, 50)), 4),
             "p99_ms_in_batch": round(float(np.percentile(svc_ms, 99)), 4),
