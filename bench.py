@@ -101,11 +101,12 @@ def load_traffic(workload_key):
     return t
 
 
-def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors", lockstep=None):
+def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors", lockstep=None, skw=None):
     """The oracle's search timed on the host cores over a growing prefix of the queries
     until about `seconds` of CPU work.  lockstep=(M2, L2, sync keywords): also the one-thread
     latency of the oracle at that point (Algorithm 3 with M2 workers, emulated in sequence)."""
     import oracle
+    skw = skw or SYNCS["adaptive"]
     adj_h = adj.cpu().numpy()
     nq = w.queries.shape[0]
     nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -113,8 +114,7 @@ def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors", lockstep=
     while t_cpu < seconds and done < nq:
         n1 = min(bs, nq - done)
         s0 = time.perf_counter()
-        oracle.speedann(w.base, adj_h, entry, w.queries[done:done + n1], k, L, M, sync="adaptive", rho=0.8,
-                        staged=True, metric=w.metric)
+        oracle.speedann(w.base, adj_h, entry, w.queries[done:done + n1], k, L, M, metric=w.metric, **skw)
         t_cpu += time.perf_counter() - s0
         done += n1
         bs = min(bs * 2, 2048)
@@ -122,8 +122,7 @@ def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors", lockstep=
     lat = []
     for i in range(min(100, nq)):
         s0 = time.perf_counter()
-        oracle.speedann(w.base, adj_h, entry, w.queries[i:i + 1], k, L, M, sync="adaptive", rho=0.8, staged=True,
-                        metric=w.metric)
+        oracle.speedann(w.base, adj_h, entry, w.queries[i:i + 1], k, L, M, metric=w.metric, **skw)
         lat.append((time.perf_counter() - s0) * 1e3)
     model = ""
     try:
@@ -132,13 +131,13 @@ def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors", lockstep=
     except OSError:
         pass
     cpu = {"value": round(done / t_cpu, 1), "unit": "queries/s", "cores": nthreads, "kind": "oracle",
-           "sample": f"first {done} of the {nq} queries, same graph, {storage}, M={M}, L={L}, adaptive rho 0.8 "
-                     f"staged, lockstep emulation of Algorithm 3 in plain C, one query per OpenMP thread",
+           "sample": f"first {done} of the {nq} queries, same graph, {storage}, M={M}, L={L}, schedule {skw}, "
+                     f"lockstep emulation of Algorithm 3 in plain C, one query per OpenMP thread",
            "cpu_model": model,
            "latency_p50_ms": round(float(np.percentile(lat, 50)), 4),
            "latency_p99_ms": round(float(np.percentile(lat, 99)), 4),
            "latency_sample": f"first {len(lat)} queries one at a time, one thread, host wall time"}
-    if lockstep is not None and tuple(lockstep[:2]) != (M, L):
+    if lockstep is not None and (tuple(lockstep[:2]) != (M, L) or lockstep[2] != skw):
         M2, L2, skw = lockstep
         lat2 = []
         for i in range(min(50, nq)):
@@ -630,6 +629,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--M", type=int, default=0, help="time this walker count only (0: sweep)")
     ap.add_argument("--L", type=int, default=0, help="with --M, time this L (0: sweep)")
+    ap.add_argument("--sync", choices=["all", "adaptive", "bsp", "static8"], default="all",
+                    help="schedules to sweep: all = adaptive at every M and M = 2 merging after every step")
     ap.add_argument("--sweep-json", default="")
     ap.add_argument("--order", choices=["none", "degree", "bfs"], default="bfs",
                     help="vertex renumbering of the SIFT-shaped index (setup, not timed)")
@@ -703,35 +704,40 @@ def main():
             p = params[(M, L, sync)] = B.make_params(**SYNCS[sync])
         return ix.search(q, k, L, M, params=p, stats=stats, out=out)
 
-    def time_launches(M, L, reps):
-        out = run(M, L)
+    def time_launches(M, L, reps, sync="adaptive"):
+        out = run(M, L, sync=sync)
         out = (out.ids, out.dists, None)
         torch.cuda.synchronize()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for a, b in evs:
             a.record()
-            run(M, L, out=out)
+            run(M, L, out=out, sync=sync)
             b.record()
         torch.cuda.synchronize()
         return [a.elapsed_time(b) for a, b in evs]
 
     # ---------------------------------------------------------------- operating points
+    # candidates: the adaptive schedule at every M, and two walkers merging after every
+    # local step (Top-2, which the single-worker kernel runs in one wavefront)
     sweep = []
     Ms = [args.M] if args.M else M_SWEEP
+    cands = [(Mx, sx) for Mx in Ms for sx in (["adaptive"] if args.sync == "all" else [args.sync])]
+    if args.sync == "all" and (not args.M or args.M == 2):
+        cands.append((2, "bsp"))
     best = None
-    for M in Ms:
+    for M, sync in cands:
         Ls = [args.L] if args.L else L_SWEEP
         for L in Ls:
-            r = run(M, L, stats=True)
+            r = run(M, L, stats=True, sync=sync)
             rec = recall_at_k(r.ids, gt, k).mean().item()
-            ms = sorted(time_launches(M, L, 3))[1]
+            ms = sorted(time_launches(M, L, 3, sync))[1]
             st = r.stats[:, :6].double().mean(0).tolist()
-            row = {"M": M, "L": L, "recall": round(rec, 5), "ms": round(ms, 3), "qps": round(args.nq / ms * 1e3),
+            row = {"M": M, "sync": sync, "L": L, "recall": round(rec, 5), "ms": round(ms, 3), "qps": round(args.nq / ms * 1e3),
                    "dist_comps": round(st[3], 1), "expansions": round(st[2], 1), "substeps": round(st[1], 1),
                    "spilled": float((r.stats[:, 5] & 4 != 0).float().mean().item()),
                    "flagged": int((r.stats[:, 5] & 3 != 0).sum().item())}
             sweep.append(row)
-            log(f"M={M:2d} L={L:4d} recall={rec:.4f} {ms:8.3f} ms/batch qps={row['qps']:>9} "
+            log(f"M={M:2d} {sync:8s} L={L:4d} recall={rec:.4f} {ms:8.3f} ms/batch qps={row['qps']:>9} "
                 f"D={row['dist_comps']:.0f} E={row['expansions']:.0f} sub={row['substeps']:.0f} "
                 f"spill={row['spilled']:.2f} flagged={row['flagged']}")
             if rec >= TARGET:
@@ -745,30 +751,30 @@ def main():
     if not reached:
         best = max(sweep, key=lambda r: (r["recall"], r["qps"]))
         log(f"recall {TARGET} not reached; timing the best-recall point {best}")
-    M, L = best["M"], best["L"]
+    M, L, SYNC = best["M"], best["L"], best["sync"]
 
     # ---------------------------------------------------------------- timed region
-    r = run(M, L, stats=True)
+    r = run(M, L, stats=True, sync=SYNC)
     torch.cuda.synchronize()
     stats = r.stats.cpu().numpy()
     recall = recall_at_k(r.ids, gt, k).mean().item()
     out = (torch.empty_like(r.ids), torch.empty_like(r.dists), None)
     for _ in range(args.warmup):
-        run(M, L, out=out)
+        run(M, L, out=out, sync=SYNC)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for a, b in evs:
         a.record()
-        run(M, L, out=out)
+        run(M, L, out=out, sync=SYNC)
         b.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     launch_ms = np.array([a.elapsed_time(b) for a, b in evs])
     ms_per_step = wall * 1e3 / args.steps
     qps = args.nq / (ms_per_step / 1e3)
-    log(f"timed M={M} L={L}: {ms_per_step:.3f} ms/step, kernel {launch_ms.mean():.3f} ms, QPS {qps:,.0f}")
+    log(f"timed M={M} {SYNC} L={L}: {ms_per_step:.3f} ms/step, kernel {launch_ms.mean():.3f} ms, QPS {qps:,.0f}")
 
     # in-batch service time of each query (device real-time counter, 100 MHz)
     t = stats.view(np.int64)[:, 3:5]
@@ -805,9 +811,9 @@ def main():
     # candidates: every M at its adaptive operating point, and for the latency widths
     # M = 8, 16 the other schedules of the paper at their own smallest L reaching the target
     # (merging after every local step is Top-M; within one workgroup a merge is cheap)
-    ops = {(s["M"], "adaptive"): s["L"] for s in sweep if s["recall"] >= TARGET} if reached else {(M, "adaptive"): L}
-    op_recall = {(s["M"], "adaptive"): s["recall"] for s in sweep if s["recall"] >= TARGET}
-    if reached and nl > 0 and not args.M:
+    ops = {(s["M"], s["sync"]): s["L"] for s in sweep if s["recall"] >= TARGET} if reached else {(M, SYNC): L}
+    op_recall = {(s["M"], s["sync"]): s["recall"] for s in sweep if s["recall"] >= TARGET}
+    if reached and nl > 0 and not args.M and args.sync == "all":
         for Mx in (8, 16):
             for sync in ("bsp", "static8"):
                 for Lx in L_SWEEP:
@@ -827,7 +833,7 @@ def main():
                              "p99_ms": round(float(np.percentile(a, 99)), 4), "queries": len(a)}
             log(f"batch-1 latency sample M={Mx} {sync} L={Lx}: p50 {lat_by_M[key]['p50_ms']:.3f} ms")
     best_key = min(lat_by_M, key=lambda c: lat_by_M[c]["p50_ms"]) if lat_by_M else None
-    Mlat, sync_lat = (lat_by_M[best_key]["M"], lat_by_M[best_key]["sync"]) if best_key else (M, "adaptive")
+    Mlat, sync_lat = (lat_by_M[best_key]["M"], lat_by_M[best_key]["sync"]) if best_key else (M, SYNC)
     Llat = ops.get((Mlat, sync_lat), L)
     lat = batch1(Mlat, Llat, nl, sync_lat)
     log(f"batch-1 latency M={Mlat} {sync_lat} L={Llat}: p50 {np.percentile(lat, 50):.3f} ms, "
@@ -839,7 +845,7 @@ def main():
     E = stats[:, 2].astype(np.float64)
     bytes_launch = float((D * d * 4 + E * R * 4 + d * 4 + k * 8).sum())
     achieved = bytes_launch / (launch_ms.mean() / 1e3) / 1e9
-    workload_key = f"sift-like-{args.n}x{d}-nq{args.nq}-M{M}-L{L}-order-{args.order}"
+    workload_key = f"sift-like-{args.n}x{d}-nq{args.nq}-M{M}-{SYNC}-L{L}-order-{args.order}"
     tr = load_traffic(workload_key)
     gc = B.gather_ceiling(base)
     log(f"gather ceiling: {gc['GBs']:.0f} GB/s for random {gc['row_bytes']}-byte rows")
@@ -853,7 +859,7 @@ def main():
 
     # ---------------------------------------------------------------- CPU oracle baseline
     cpu = None if args.no_cpu else cpu_oracle(w, adj0, entry0, k, L, M, args.cpu_seconds,
-                                              lockstep=(Mlat, Llat, SYNCS[sync_lat]))
+                                              lockstep=(Mlat, Llat, SYNCS[sync_lat]), skw=SYNCS[SYNC])
 
     res = {
         "metric": "QPS and p50/p99 latency at recall@10=0.99, 1M×128 SIFT-shaped, 1 GPU",
@@ -875,7 +881,7 @@ def main():
             "graph": f"exact 64-NN, relative-neighbourhood prune to R={R}, repair (keep_local 1), medoid entry",
             "graph_build_s": round(t_graph, 1),
             "vertex_order": args.order,
-            "M": M, "L": L, "sync": "adaptive", "rho": 0.8, "staged": True,
+            "M": M, "L": L, **SYNCS[SYNC],
             "recall@10": round(recall, 5), "target_reached": reached,
             "storage": "f32 vectors, int32 adjacency",
             "p50_ms_batch1": round(float(np.percentile(lat, 50)), 4),

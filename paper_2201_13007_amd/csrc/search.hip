@@ -48,9 +48,14 @@ int ilog2_exact(int64_t v)
 }
 
 // One worker with no LDS table runs the single-worker kernel, whose workspace table holds
-// 32-bit entries (id + 1) and needs no claim order; every other case runs the general
-// kernel with 64-bit entries that carry the claim tag.
-bool compact_table(int M, int llog2) { return M == 1 && llog2 == 0; }
+// 32-bit entries (id + 1) and needs no claim order; so do two workers that merge after
+// every local step over rows of at most 32 entries (both rows fill one wavefront, and with
+// every-step merges one queue holds what the two local queues would).  Every other case
+// runs the general kernel with 64-bit entries that carry the claim tag.
+bool compact_table(int M, int llog2, int sync, int R)
+{
+    return llog2 == 0 && (M == 1 || (M == 2 && sync == SA_SYNC_BSP && R <= 32));
+}
 
 void resolve_params(const sa_search_params &in, int L, int M, int R, int &llog2, int &glog2, int &max_sub)
 {
@@ -77,7 +82,7 @@ void resolve_params(const sa_search_params &in, int L, int M, int R, int &llog2,
         // three-quarter limit sits near 24 L, several times the 8 L or so a search visits
         // at these R; the general table keeps 64 L.  8 M R more cover the M R vertices one
         // local step may add on top.
-        int64_t want = (compact_table(M, llog2) ? 32ll : 64ll) * L + 8ll * M * R;
+        int64_t want = (compact_table(M, llog2, in.sync, R) ? 32ll : 64ll) * L + 8ll * M * R;
         if (want < 4096) want = 4096;
         // a re-rank takes the last 1025 entries of the slot list, beyond the three
         // quarters the search may fill: at least 8192 slots
@@ -86,7 +91,7 @@ void resolve_params(const sa_search_params &in, int L, int M, int R, int &llog2,
     }
 }
 
-size_t bytes_per_slot(int M, int llog2) { return compact_table(M, llog2) ? 8 : 16; }
+size_t bytes_per_slot(int M, int llog2, int sync, int R) { return compact_table(M, llog2, sync, R) ? 8 : 16; }
 
 }  // namespace
 
@@ -105,7 +110,7 @@ size_t search_workspace_bytes(int64_t nq, int32_t L, int32_t M, const sa_search_
 {
     int llog2, glog2, max_sub;
     resolve_params(p, L, M, R, llog2, glog2, max_sub);
-    return (size_t)nq * (bytes_per_slot(M, llog2) << glog2);
+    return (size_t)nq * (bytes_per_slot(M, llog2, p.sync, R) << glog2);
 }
 
 namespace {
@@ -177,7 +182,7 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
         return set_error(SA_EINVAL, "lds_hash_slots too small for M * R new vertices per local step");
     if ((int64_t(1) << glog2) * 3 / 4 < (int64_t)a.M * a.R + 1)
         return set_error(SA_EINVAL, "ws_hash_slots too small for M * R new vertices per local step");
-    const size_t need = (size_t)a.nq * (bytes_per_slot(a.M, llog2) << glog2);
+    const size_t need = (size_t)a.nq * (bytes_per_slot(a.M, llog2, a.p.sync, a.R) << glog2);
     if (a.ws_bytes < need)
         return set_error(SA_ECAPACITY, "workspace of %zu bytes is smaller than the %zu bytes needed", a.ws_bytes, need);
     if (a.workspace == nullptr && need > 0) return set_error(SA_EINVAL, "workspace is NULL");
@@ -204,7 +209,7 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     // claims out of HBM.  With fewer queries in flight the emptier region-sized table is
     // faster.  A query that outgrows its table moves into one twice as large, up to the
     // region's 2^glog2.
-    if (a.p.ws_hash_init > 0 && compact_table(a.M, llog2)) {
+    if (a.p.ws_hash_init > 0 && compact_table(a.M, llog2, a.p.sync, a.R)) {
         // (used by one walker only; larger than the region means the region)
         const int t = ilog2_exact(a.p.ws_hash_init);
         if (t < 7 || (int64_t(1) << t) != a.p.ws_hash_init)
@@ -226,7 +231,7 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     if (a.nq == 0) return SA_OK;
     if (a.d > 1024) return set_error(SA_EUNSUPPORTED, "d=%d exceeds 1024", a.d);
     int rc;
-    const bool compact = compact_table(a.M, llog2);
+    const bool compact = compact_table(a.M, llog2, a.p.sync, a.R);
     A.int_lo = a.int_lo; A.int_hi = a.int_hi; A.acc_pass = -1;
     if (compact) {
         if (a.dtype == SA_BF16) rc = launch_search_single_bf16(A, a.nq, stream);
@@ -249,7 +254,7 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     }
     if (rc == SA_OK && a.p.rerank != 0) {
         // the list sits at the end of the slot list, which follows the table in each region
-        const int64_t stride = (int64_t)bytes_per_slot(a.M, llog2) << glog2;
+        const int64_t stride = (int64_t)bytes_per_slot(a.M, llog2, a.p.sync, a.R) << glog2;
         const int64_t list_off = ((int64_t)(compact ? 4 : 8) << glog2) + 4 * ((int64_t(1) << glog2) - 1025);
         rc = launch_rerank(a.vec32, a.ld32, a.queries, a.ldq, a.nq, a.d, a.metric, a.k, a.L, a.workspace, stride,
                            list_off, a.ids, a.dists, a.order, a.qk, A.ldo, stream);

@@ -76,6 +76,20 @@ __device__ __forceinline__ int first_unchecked(const Queue<NI> &Q)
     return 64 * NI;
 }
 
+// first unchecked position after p (p may be 64 NI)
+template <int NI>
+__device__ __forceinline__ int next_unchecked(const Queue<NI> &Q, int p)
+{
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int lo = p + 1 - 64 * i;   // positions of this slot below lo are excluded
+        const uint64_t keep = lo <= 0 ? ~0ull : (lo >= 64 ? 0ull : (~0ull << lo));
+        const uint64_t b = low_bits(Q.len - 64 * i) & ~Q.chk[i] & keep;
+        if (b) return 64 * i + __builtin_ctzll(b);
+    }
+    return 64 * NI;
+}
+
 // Uniform position p: the key is read with a lane read in the branch of its slot, and a
 // flag is set by a masked update of every slot.  Folding either into an access indexed by
 // p / 64 would make the compiler move the arrays to scratch memory.
@@ -277,9 +291,18 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
 
     const int max_sub = A.max_substeps;
     const int32_t n = (int32_t)A.n;
+    // Two walkers merging after every local step (Top-2, M = 2 with the every-step schedule,
+    // R <= 32) also run here: the merge of their two local queues is the queue with both
+    // expansions' new vertices inserted, so one queue serves.  Walker 0 expands the first
+    // unchecked entry on lanes 0-31, walker 1 the second on lanes 32-63.
+    const bool two = A.M == 2;
+    const bool second = two && lane >= 32;
+    int m = two && !A.staged ? 2 : 1;   // walkers active in the next step (staged: 1, then 2)
+    int nexp = 0;
     // this lane's entry of an adjacency row (R <= 64); lanes past R load entry 0 and drop it
-    const int32_t *const adj_lane = A.adj + (lane < R ? lane : 0);
-    int32_t pv = -1, pu = -1;   // vertex whose row is prefetched, and this lane's entry of it
+    const int aidx = two ? (lane & 31) : lane;
+    const int32_t *const adj_lane = A.adj + (aidx < R ? aidx : 0);
+    int32_t pv = -1, pv2 = -1, pu = -1;   // vertices whose rows are prefetched, and this lane's entry
     int cur = 0;
     bool stop = false;
     while (cur < Q.len && !stop) {
@@ -295,13 +318,27 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             sub_in_step++;
             const int32_t v = key_id(get_key(Q, cur));
             mark_checked(Q, cur);
+            int32_t v2 = -1;
+            if (m == 2) {
+                const int c2 = first_unchecked(Q);
+                if (c2 < Q.len) {
+                    v2 = key_id(get_key(Q, c2));
+                    mark_checked(Q, c2);
+                }
+            }
+            nexp += v2 >= 0 ? 2 : 1;
+            const int32_t vl = second ? v2 : v;   // the vertex whose row this lane reads
             int32_t u = pu;
-            if (v != pv) u = adj_lane[(int64_t)v * R];
-            // prefetch the row of the next candidate while this step runs
+            if (vl != (second ? pv2 : pv)) u = adj_lane[(int64_t)(vl >= 0 ? vl : v) * R];
+            // prefetch the rows of the next candidates while this step runs
             const int nxt = first_unchecked(Q);
             pv = nxt < Q.len ? key_id(get_key(Q, nxt)) : v;
-            pu = adj_lane[(int64_t)pv * R];
-            if (lane >= R || u < 0 || u >= n) u = -1;   // padding and malformed entries
+            if (two) {
+                const int nx2 = next_unchecked(Q, nxt);
+                pv2 = nx2 < Q.len ? key_id(get_key(Q, nx2)) : pv;
+            }
+            pu = adj_lane[(int64_t)(second ? pv2 : pv) * R];
+            if (aidx >= R || vl < 0 || u < 0 || u >= n) u = -1;   // idle walker, padding, malformed entries
             bool fresh = false;
             const uint32_t hs = ((uint32_t)u * 2654435761u) >> (32 - SEEN_LOG2);
             const bool ask = u >= 0 && seen[hs] != (uint32_t)u + 1u;
@@ -325,9 +362,9 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             const uint64_t sbits = __ballot(mk < worst);
             const int U = sbits ? insert_batch(Q, L, mk, sbits, nkey) : L;
             cur = first_unchecked(Q);
-            if (nslot + R > cap) {
+            if (nslot + (two ? 2 * R : R) > cap) {
                 if (t2 < g2) {
-                    // (one doubling suffices: nslot <= cap before, and R <= 64 < cap)
+                    // (one doubling suffices: nslot <= cap before, and at most 64 new < cap)
                     grow_table(tbl, slots, nslot, ++t2);
                     cap = (3 << t2) / 4;
                     flags |= SA_QFLAG_SPILLED;
@@ -344,6 +381,7 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             if (cur >= Q.len || merge_now) break;
         }
         merges++;   // the queue is S unchanged
+        if (two) m = 2;
     }
 
     if (A.rerank != 0) {
@@ -374,7 +412,7 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
         sa_query_stats st;
         st.global_steps = gsteps;
         st.substeps = substeps;
-        st.expansions = substeps;
+        st.expansions = nexp;
         st.dist_comps = nslot;
         st.merges = merges;
         st.flags = flags;

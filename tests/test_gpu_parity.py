@@ -291,6 +291,17 @@ def test_search_sift_shaped(B, sift_setup, L, M):
         assert_search_equal(g, e, exact=True, label=f"sift L={L} M={M} {sync}")
 
 
+@pytest.mark.parametrize("staged", [True, False])
+@pytest.mark.parametrize("L", [48, 176, 300])
+def test_search_two_walkers_every_step(B, sift_setup, L, staged):
+    # M = 2 merging after every local step (Top-2) runs in the single-worker kernel, one
+    # walker per half wavefront; ids, distances and all five counters equal the oracle's
+    w, adj, entry = sift_setup
+    print(f"case: search sift-20k M=2 every-step merges L={L} staged={staged}", flush=True)
+    g, e = run_both(B, w.base, adj, entry, w.queries, 10, L, 2, sync="bsp", staged=staged)
+    assert_search_equal(g, e, exact=True, label=f"sift M=2 bsp L={L} staged={staged}")
+
+
 @pytest.mark.parametrize("L", [160, 288, 352, 416, 480])
 def test_search_single_queue_sizes(B, sift_setup, L):
     # one walker: every register-queue size the single-worker kernel is compiled for
