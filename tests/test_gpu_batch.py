@@ -126,19 +126,22 @@ def test_batch_graph_replay(B, gist):
         np.testing.assert_array_equal(host(again.ids), e_ids)
 
 
-def test_batch_one_class_and_sift(B):
+@pytest.mark.parametrize("sync", ["adaptive", "bsp"])
+def test_batch_one_class_and_sift(B, sync):
+    # bsp: two walkers merging after every step, which run in one wavefront
     w = synth.sift_like(n=5000, nq=40)
     adj, entry, _ = oracle.build_graph(w.base, 32, 24, "rng", do_repair=True)
     L = np.full(40, 96, np.int32)
     k = np.full(40, 10, np.int32)
     M = np.full(40, 2, np.int32)
-    print("case: batch sift-5000 one class M=2 L=96", flush=True)
+    print(f"case: batch sift-5000 one class M=2 L=96 {sync}", flush=True)
     ix = B.Index(dev(w.base), dev(adj), entry)
-    r = B.Batch(ix, L, k, M).run(dev(w.queries), stats=True)
-    eids, ed, est = oracle.speedann(w.base, adj, entry, w.queries, 10, 96, 2)
+    r = B.Batch(ix, L, k, M, sync=sync).run(dev(w.queries), stats=True)
+    eids, ed, est = oracle.speedann(w.base, adj, entry, w.queries, 10, 96, 2, sync=sync)
     np.testing.assert_array_equal(host(r.ids), eids)
     np.testing.assert_array_equal(host(r.dists), ed)   # integer data: exact
-    np.testing.assert_array_equal(host(r.stats)[:, 3], est["dist_comps"])
+    for j, name in enumerate(["global_steps", "substeps", "expansions", "dist_comps", "merges"]):
+        np.testing.assert_array_equal(host(r.stats)[:, j], est[name], err_msg=name)
 
 
 def test_batch_errors(B, gist):
