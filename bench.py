@@ -187,14 +187,16 @@ def deep_main(args, torch, B, synth, dev):
     torch.cuda.synchronize()
     log(f"ground truth in {time.time() - t0:.2f}s")
 
-    M = args.M or 1
+    # default: two walkers merging after every step (one wavefront), the fastest form found
+    M = args.M or 2
+    skw = SYNCS[args.sync if args.sync != "all" else ("bsp" if M == 2 else "adaptive")]
     forms = [("f32", 0), ("bf16", 0), ("bf16", -1), ("fp8", 0), ("fp8", -1)]
     index = {s: B.Index(base, adj, entry, metric=w.metric, dtype=s) for s in ("f32", "bf16", "fp8")}
     base64 = w.base.astype(np.float64)
     q64 = w.queries.astype(np.float64)
 
     def run(storage, rr, L, stats=False, out=None):
-        p = B.make_params(sync="adaptive", rho=0.8, staged=True, rerank=rr)
+        p = B.make_params(rerank=rr, **skw)
         return index[storage].search(queries, k, L, M, params=p, stats=stats, out=out)
 
     def measure(storage, rr, L, reps):
@@ -265,7 +267,7 @@ def deep_main(args, torch, B, synth, dev):
                 "algorithmic_bytes_per_launch": round(bytes_launch),
                 "kernel_ms": round(float(launch_ms.mean()), 4),
                 "note": "search and re-rank launches timed together" if rr else "search launch"}
-    cpu = None if args.no_cpu else cpu_oracle(w, adj, entry, k, L32, M, args.cpu_seconds)
+    cpu = None if args.no_cpu else cpu_oracle(w, adj, entry, k, L32, M, args.cpu_seconds, skw=skw)
     res = {
         "metric": "QPS and recall@10 by vector storage (fp32 / bf16 / fp8-e4m3, exact fp32 re-rank), "
                   "distance error vs FP64, 1M×96 DEEP-shaped inner product, 1 GPU",
@@ -278,7 +280,7 @@ def deep_main(args, torch, B, synth, dev):
             "workload": f"deep-like {args.n}x{d} (512-component mixture, sigma 1, coordinate variance 1/i, "
                         f"unit norm), {nq} queries, k={k}, inner product",
             "graph": f"exact 64-NN, relative-neighbourhood prune to R={R}, repair (keep_local 1), medoid entry",
-            "graph_build_s": round(t_graph, 1), "M": M, "sync": "adaptive", "rho": 0.8, "staged": True,
+            "graph_build_s": round(t_graph, 1), "M": M, **skw,
             "timed": {"storage": storage, "rerank": best["rerank"], "L": L, "recall@10": row["recall"]},
             "operating_points": points,
             "at_f32_L": at_f32,
