@@ -265,8 +265,9 @@ def tiny_setup():
     return w, adj, entry
 
 
-@pytest.mark.parametrize("M", [1, 4])
-@pytest.mark.parametrize("sync,staged", [("adaptive", True), ("adaptive", False), ("bsp", False), ("static", True)])
+@pytest.mark.parametrize("M", [1, 2, 4])
+@pytest.mark.parametrize("sync,staged", [("adaptive", True), ("adaptive", False), ("bsp", False), ("bsp", True),
+                                         ("static", True)])
 def test_search_tiny(B, tiny_setup, M, sync, staged):
     w, adj, entry = tiny_setup
     print(f"case: search tiny M={M} sync={sync} staged={staged}", flush=True)
