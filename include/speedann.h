@@ -260,7 +260,9 @@ size_t sa_search_workspace_bytes(const sa_index *index, int64_t nq, int32_t k, i
                                  const sa_search_params *params);
 
 /* Intra-query parallel search (Algorithm 3; Algorithm 1 when M = 1), one workgroup per
- * query and one wavefront per worker:
+ * query and one wavefront per worker (two workers that merge after every local step,
+ * SA_SYNC_BSP, over adjacency rows of at most 32 entries share one wavefront; results and
+ * counters are the same either way):
  *   queries_dev  nq x d float32, stride ldq floats (16-byte aligned rows); d <= 1024
  *   k, L         results per query and queue capacity, 1 <= k <= L <= 1024
  *   M            workers (the paper's T, the maximum expansion width), 1 <= M <= 16
