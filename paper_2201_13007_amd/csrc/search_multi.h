@@ -3,6 +3,8 @@
 #pragma once
 #include "search_body.h"
 
+#include <atomic>
+
 namespace sa {
 namespace search_detail {
 
@@ -16,9 +18,19 @@ template <int LPV, int NI, int DT>
 hipError_t launch1(const KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s)
 {
     auto k = search_multi<LPV, NI, DT>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    // the dynamic LDS limit is raised to the whole 160 KB once per instantiation and
+    // device, not on every launch (the latency path launches one query at a time)
+    static std::atomic<uint64_t> raised{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(raised.load(std::memory_order_acquire) & bit)) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024);
+        if (e != hipSuccess) return e;
+        raised.fetch_or(bit, std::memory_order_acq_rel);
+    }
     hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64 * M), lds, s, A);
     return hipGetLastError();
 }

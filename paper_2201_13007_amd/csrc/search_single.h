@@ -17,8 +17,10 @@
 // query's workspace region, claimed with compare-and-swap.  The table in use is a prefix
 // of the region that doubles (rehashing the set) when it passes three quarters full.  An
 // LDS array of recently claimed or rejected ids sits in front of it: a neighbour found
-// there is visited and needs no compare-and-swap.  The slots a query fills are listed
-// after the table and zeroed again before it ends.
+// there is visited and needs no compare-and-swap.  When the query ends it clears the
+// table in use with whole-line stores, which leaves the region zero for the next launch:
+// clearing only the slots it filled would write each of their lines back a second time
+// (they are long evicted by then), and listing them would cost writes of its own.
 //
 // Distances.  LPV lanes share one vector, each lane four float4 chunks (c = g, g + LPV,
 // ...), accumulated in double precision (in float32 where the data and the query are
@@ -203,22 +205,40 @@ __device__ __forceinline__ uint32_t claim(uint32_t *T, int log2cap, uint32_t u, 
     return NO_SLOT;
 }
 
-// Moves the visited set from the table in use into one twice as large, 2^t2 entries at
-// the same address (the region holds the largest): every entry is taken out through the
-// slot list (exchanged for 0) and inserted again, and the slot list then holds the new
-// slots.  The whole wavefront takes part.
-__device__ __forceinline__ void grow_table(uint32_t *tbl, uint32_t *slots, int nslot, int t2)
+// Moves the visited set from the table in use (2^t1 entries) into one twice as large,
+// 2^t2 entries at the same address (the region holds the largest; past the table in use
+// it is zero).  The entries are copied out to scratch (the second half of the region) and
+// the table is cleared; then they are inserted again and scratch is cleared.  Returns the
+// number of entries moved.  The whole wavefront takes part.
+__device__ __forceinline__ int grow_table(uint32_t *tbl, uint32_t *scratch, int t1, int t2)
 {
     const int lane = __lane_id();
-    for (int i = lane; i < nslot; i += 64) slots[i] = atomicExch(&tbl[slots[i]], 0u);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    for (int i = lane; i < nslot; i += 64) {
-        bool fresh;
-        slots[i] = claim(tbl, t2, slots[i] - 1u, &fresh);
+    int cnt = 0;
+    for (int b = 0; b < (1 << t1); b += 64) {   // 2^t1 >= 64 entries
+        const uint32_t e = tbl[b + lane];
+        const uint64_t m = __ballot(e != 0u);
+        if (e != 0u) scratch[cnt + __popcll(m & lanemask_lt())] = e;
+        tbl[b + lane] = 0u;
+        cnt += __popcll(m);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     __builtin_amdgcn_wave_barrier();
+    for (int i = lane; i < cnt; i += 64) {
+        bool fresh;
+        (void)claim(tbl, t2, scratch[i] - 1u, &fresh);
+        scratch[i] = 0u;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    return cnt;
+}
+
+// Zeroes the first 2^t entries of tbl (2^t >= 64, 16-byte aligned) with 16-byte stores.
+__device__ __forceinline__ void clear_table(uint32_t *tbl, int t)
+{
+    uint4 *const p = reinterpret_cast<uint4 *>(tbl);
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = __lane_id(); i < (1 << (t - 2)); i += 64) p[i] = z;
 }
 
 template <int LPV, int NI, bool L2, int DT, bool ACC32>
@@ -239,6 +259,8 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
     const int L = A.qL ? A.qL[qi] : A.L;
     const int kq = A.qk ? A.qk[qi] : A.k;
     const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+    // the second half of the region: scratch while the table grows, and the list handed
+    // to the re-rank kernel
     uint32_t *const slots = tbl + (1u << g2);
     // the table in use is the first 2^t2 entries of the region's 2^g2; it doubles when
     // the visited set would pass three quarters of it
@@ -283,8 +305,7 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
         if (lane == 0) Q.k[0] = k0;
         Q.len = 1;
         bool fresh = false;
-        const uint32_t s0 = lane == 0 ? claim(tbl, t2, (uint32_t)A.entry, &fresh) : 0u;
-        if (lane == 0) slots[0] = s0;
+        if (lane == 0) (void)claim(tbl, t2, (uint32_t)A.entry, &fresh);
         nslot = 1;
     }
     __builtin_amdgcn_wave_barrier();
@@ -342,15 +363,11 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             bool fresh = false;
             const uint32_t hs = ((uint32_t)u * 2654435761u) >> (32 - SEEN_LOG2);
             const bool ask = u >= 0 && seen[hs] != (uint32_t)u + 1u;
-            const uint32_t slot = ask ? claim(tbl, t2, (uint32_t)u, &fresh) : NO_SLOT;
+            if (ask) (void)claim(tbl, t2, (uint32_t)u, &fresh);
             if (ask) seen[hs] = (uint32_t)u + 1u;
             const uint64_t fm = __ballot(fresh);
             const int nnew = __popcll(fm);
-            if (fresh) {
-                const int r = __popcll(fm & lanemask_lt());
-                slots[nslot + r] = slot;
-                sid[r] = u;
-            }
+            if (fresh) sid[__popcll(fm & lanemask_lt())] = u;
             nslot += nnew;
             __builtin_amdgcn_wave_barrier();
             distances<LPV, L2, DT, ACC32>(V, A.d, qs, sid, nnew, nkey);
@@ -365,7 +382,8 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             if (nslot + (two ? 2 * R : R) > cap) {
                 if (t2 < g2) {
                     // (one doubling suffices: nslot <= cap before, and at most 64 new < cap)
-                    grow_table(tbl, slots, nslot, ++t2);
+                    ++t2;
+                    (void)grow_table(tbl, slots, t2 - 1, t2);
                     cap = (3 << t2) / 4;
                     flags |= SA_QFLAG_SPILLED;
                 } else {
@@ -404,10 +422,7 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
         }
     }
     // leave the workspace zero-filled for the next launch
-    for (int i = lane; i < nslot; i += 64) {
-        tbl[slots[i]] = 0u;
-        slots[i] = 0u;
-    }
+    clear_table(tbl, t2);
     if (lane == 0 && A.stats) {
         sa_query_stats st;
         st.global_steps = gsteps;

@@ -1,9 +1,12 @@
-"""Full-size checks on the SIFT-shaped 1M x 128 workload, in the configuration bench.py
-times (graph built on the GPU, M = 1 and M = 2 at L = 384, adaptive rho 0.8, staged).
+"""Full-size checks on the SIFT-shaped 1M x 128 workload (graph built on the GPU).
 
-The oracle cannot build a 1M graph or search it for every query in test time, so this
-checks sampled outputs the oracle computes one by one, and properties that hold at any
-size.  Data are integer-valued, so every distance is exact and compared bit for bit.
+The configuration bench.py times (breadth-first renumbering, two walkers merging after
+every local step, staged, L = 192, k = 10) is compared with the oracle id for id,
+distance for distance and counter for counter on all 10,000 queries: the oracle searches
+the relabelled graph (the search of a renumbered index is the search of the relabelled
+graph) and its ids are mapped back.  The graph build itself is too large for the oracle;
+its kNN rows are checked on a sample, and the graph on properties that hold at any size.
+Data are integer-valued, so every distance is exact and compared bit for bit.
 """
 import numpy as np
 import pytest
@@ -116,3 +119,37 @@ def test_fullsize_search_renumbered(full):
     print(f"   sampled recall@10 = {rec:.4f}", flush=True)
     assert rec >= 0.97
     assert (d[sample] >= gd).all()
+
+
+def test_fullsize_bench_config_equals_oracle(full):
+    # exactly the timed configuration: renumbered index with an id map, M = 2 merging
+    # after every local step, staged, L = 192, k = 10, float32 accumulation (integer data)
+    B, w, base, adj, entry, info = full
+    base2, adj2, entry2, perm = B.reorder(base, adj, entry, "bfs")
+    ix = B.Index(base2, adj2, entry2, id_map=perm)
+    assert ix.integer_range is not None
+    q = torch.from_numpy(w.queries).cuda()
+    print("case: full-size bench configuration M=2 bsp staged L=192, all 10000 queries vs oracle", flush=True)
+    r = ix.search(q, 10, 192, 2, stats=True, sync="bsp", staged=True)
+    torch.cuda.synchronize()
+    ids, d = r.ids.cpu().numpy(), r.dists.cpu().numpy()
+    st = r.stats.cpu().numpy()
+    assert (st[:, 5] & 3 == 0).all()
+    p = perm.cpu().numpy()
+    # the oracle's index: the original graph relabelled by the oracle, which must be the
+    # renumbered index the GPU holds
+    b2, a2, e2 = oracle.permute(w.base, adj.cpu().numpy(), entry, p)
+    assert e2 == entry2
+    np.testing.assert_array_equal(a2, adj2.cpu().numpy())
+    np.testing.assert_array_equal(b2, base2.cpu().numpy())
+    eids, ed, est = oracle.speedann(b2, a2, entry2, w.queries, 10, 192, 2, sync="bsp", staged=True)
+    eids = np.where(eids >= 0, p[np.maximum(eids, 0)], -1)
+    bad = np.nonzero((ids != eids).any(1))[0]
+    assert bad.size == 0, f"{bad.size} queries differ, first {bad[:5]}"
+    np.testing.assert_array_equal(d, ed)
+    for j, name in enumerate(("global_steps", "substeps", "expansions", "dist_comps", "merges")):
+        np.testing.assert_array_equal(st[:, j], est[name], err_msg=name)
+    gt, _ = B.knn(base, q, 10)
+    rec = oracle.recall(ids, gt.cpu().numpy()).mean()
+    print(f"   recall@10 = {rec:.4f}", flush=True)
+    assert rec >= 0.99
