@@ -28,22 +28,28 @@
  *                     which stores float32): or_quantize, or_dequantize, or_rerank
  *
  * Readings where the paper is silent (each listed in the design notes):
- *   - the starting point is marked visited when it is added (Algorithm 1 adds it
- *     without marking it);
- *   - the update position of a worker that inserted nothing that survived the
- *     truncation, or that was idle, is L; positions are 0-based after truncation;
- *   - "divide all unchecked vertices from S into LS": every local queue starts as a
- *     full copy of S; the j-th unchecked entry of S (in key order) belongs to worker
- *     j mod m; the other workers see it as FOREIGN (it occupies a slot but they never
- *     expand it);
- *   - merge: the union of S and every local queue, one entry per id, CHECKED if any
- *     copy is CHECKED, truncated to L;
- *   - the check runs after every sub-step; "M <- 2M" is capped at T.
+ *   - the starting point counts as visited as soon as it is on the list (Algorithm 1
+ *     puts it there without marking it);
+ *   - a worker's update position is its best new entry's 0-based place after the cut to
+ *     L, and L when nothing it added stayed or when it had nothing to expand;
+ *   - how a global step splits the work: each worker's local list starts as a copy of S;
+ *     the unchecked entries of S, in key order, are dealt to the workers in turn (the j-th
+ *     to worker j mod m), and in a worker's copy the entries dealt to others are FOREIGN
+ *     (they keep their places, that worker never expands them);
+ *   - merging: one entry per vertex from S and every local list, checked if any copy
+ *     is, the L best kept;
+ *   - the schedule is consulted after every round of local steps; the number of active
+ *     workers doubles up to T, never past it.
  *
- * parity pins: see tests/test_oracle*.py (exact kNN at L >= reachable set, M=1
- * reduces to Algorithm 1, synchronising every step reduces to Top-M, adaptive with
- * ratio 0 reduces to Top-M and with ratio above 1 to no synchronisation, hand-derived
- * traces under tests/golden/).
+ * Pins: tests/test_oracle.py (exact kNN when L covers the reachable set, one worker is
+ * Algorithm 1, merging after every local step is Top-M, CheckMetrics with ratio 0 merges
+ * every step and above 1 never, static schedules and the step limit on hand-derived
+ * traces under tests/golden/, exact kNN against a brute force in numpy).
+ *
+ * Trace: or_search_batch_traced also records, per query, the expansions, the entries they
+ * added and the smallest relative gap between neighbouring keys that any decision of the
+ * search depended on; tests use it to tell a disagreement caused by rounding (keys within
+ * the tolerance) from a wrong step.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -63,6 +69,7 @@ typedef struct {
     int64_t expansions;     /* vertices marked checked */
     int64_t dist_comps;     /* distances computed = size of the visited set */
     int64_t merges;         /* merges of the local queues into S */
+    int64_t flags;          /* 1: stopped by the step limit (Algorithm 3 only) */
 } or_stats;
 
 /* ---------------------------------------------------------------- distance */
@@ -163,7 +170,7 @@ static void knn_impl(const float *base, int64_t n, int d, int64_t ld, const floa
     }
 }
 
-/* ---------------------------------------------------------------- search: shared helpers */
+/* ---------------------------------------------------------------- search: common parts */
 
 typedef struct {
     const float *base;
@@ -184,93 +191,205 @@ static void emit(const entry *S, int64_t len, int k, int32_t *ids, float *dists)
     }
 }
 
+/* Optional record of one query's search, for explaining a disagreement with another
+ * implementation of it.  Every decision a search takes is an order between keys, so the
+ * smallest relative gap between two keys of distinct vertices that stand next to each
+ * other in a sorted list, within the first L + 1 places (the ones that decide what is
+ * kept, expanded and reported), bounds how far a distance may move before some decision
+ * can change.  The expansions and the entries each of them added are listed too. */
+typedef struct {
+    double min_gap;        /* |a - b| / max(|a|, |b|) of that pair; +inf if there was none */
+    int64_t gap_step;      /* local step after which the pair was seen (0: none yet) */
+    float gap_dist[2];     /* the pair's keys */
+    int32_t gap_id[2];
+    int64_t n_exp;         /* expansions, and entries they added: every one counts, */
+    int64_t n_keys;        /* even past the capacity of the lists below */
+} or_trace;
+
+typedef struct {
+    or_trace *t;           /* NULL: nothing is recorded */
+    int32_t *exp;          /* 4 ints per expansion: local step, worker, vertex, entries added */
+    float *key_dist;       /* the entries added, in order */
+    int32_t *key_id;
+    int64_t cap_exp, cap_keys;
+} tracer;
+
+/* What a search keeps besides its lists: the visited map (one byte per vertex: its distance
+ * has been computed), the counters and the trace. */
+typedef struct {
+    problem P;
+    uint8_t *visited;
+    or_stats st;
+    tracer tr;
+} search_ctx;
+
+static int ctx_open(search_ctx *c, const problem *P, const tracer *tr)
+{
+    c->P = *P;
+    memset(&c->st, 0, sizeof(c->st));
+    if (tr) c->tr = *tr;
+    else memset(&c->tr, 0, sizeof(c->tr));
+    if (c->tr.t) {
+        memset(c->tr.t, 0, sizeof(*c->tr.t));
+        c->tr.t->min_gap = INFINITY;
+        c->tr.t->gap_id[0] = c->tr.t->gap_id[1] = -1;
+    }
+    c->visited = (uint8_t *)calloc((size_t)P->n, 1);
+    return c->visited ? 0 : -2;
+}
+
+/* The list starts with the entry point alone, unchecked; the entry point counts as
+ * visited from the start (a reading: the paper adds it without marking it). */
+static int64_t put_start(search_ctx *c, entry *list, int32_t v)
+{
+    list[0].dist = pdist(&c->P, v);
+    list[0].id = v;
+    list[0].state = ST_UNCHECKED;
+    c->visited[v] = 1;
+    c->st.dist_comps = 1;
+    return 1;
+}
+
+/* Expanding v: each neighbour of v that is not visited yet, in the order of its row,
+ * becomes visited, gets its distance and is appended to the list as unchecked.  Returns
+ * how many were appended. */
+static int64_t expand(search_ctx *c, int32_t v, entry *list, int64_t *len, int64_t step, int worker)
+{
+    const int64_t before = *len;
+    const int R = c->P.R;
+    c->st.expansions++;
+    for (int r = 0; r < R; ++r) {
+        const int32_t u = c->P.adj[(int64_t)v * R + r];
+        if (u < 0 || c->visited[u]) continue;
+        c->visited[u] = 1;
+        c->st.dist_comps++;
+        list[*len].dist = pdist(&c->P, u);
+        list[*len].id = u;
+        list[*len].state = ST_UNCHECKED;
+        ++*len;
+    }
+    const int64_t added = *len - before;
+    or_trace *t = c->tr.t;
+    if (t) {
+        if (t->n_exp < c->tr.cap_exp) {
+            int32_t *e = c->tr.exp + 4 * t->n_exp;
+            e[0] = (int32_t)step; e[1] = worker; e[2] = v; e[3] = (int32_t)added;
+        }
+        t->n_exp++;
+        for (int64_t a = 0; a < added; ++a, t->n_keys++)
+            if (t->n_keys < c->tr.cap_keys) {
+                c->tr.key_dist[t->n_keys] = list[before + a].dist;
+                c->tr.key_id[t->n_keys] = list[before + a].id;
+            }
+    }
+    return added;
+}
+
+static void note_gaps(search_ctx *c, const entry *list, int64_t len, int L, int64_t step)
+{
+    or_trace *t = c->tr.t;
+    if (!t) return;
+    for (int64_t j = 0; j + 1 < len && j < L; ++j) {
+        if (list[j].id == list[j + 1].id) continue;
+        const double a = list[j].dist, b = list[j + 1].dist;
+        const double scale = fmax(fabs(a), fabs(b));
+        const double gap = scale > 0.0 ? fabs(b - a) / scale : 0.0;
+        if (gap < t->min_gap) {
+            t->min_gap = gap;
+            t->gap_step = step;
+            t->gap_dist[0] = list[j].dist; t->gap_id[0] = list[j].id;
+            t->gap_dist[1] = list[j + 1].dist; t->gap_id[1] = list[j + 1].id;
+        }
+    }
+}
+
+/* Orders list[0..len) by key and keeps its first L entries; returns the new length. */
+static int64_t order_and_cut(search_ctx *c, entry *list, int64_t len, int L, int64_t step)
+{
+    sort_entries(list, len);
+    note_gaps(c, list, len, L, step);
+    return len > L ? L : len;
+}
+
+static int64_t first_unchecked(const entry *list, int64_t len)
+{
+    for (int64_t j = 0; j < len; ++j)
+        if (list[j].state == ST_UNCHECKED) return j;
+    return -1;
+}
+
 /* ---------------------------------------------------------------- Algorithm 1 */
+
+/* Best-first search: the list keeps the L best vertices seen so far; each step expands the
+ * best one not expanded yet, until none is left. */
+static int bfis_run(const problem *P, const tracer *tr, int32_t entry_id, int k, int L, int32_t *ids, float *dists,
+                    or_stats *st)
+{
+    search_ctx c;
+    entry *S = (entry *)malloc(sizeof(entry) * (size_t)(L + P->R));
+    if (ctx_open(&c, P, tr) != 0 || !S) { free(c.visited); free(S); return -2; }
+    int64_t len = put_start(&c, S, entry_id);
+    for (;;) {
+        const int64_t i = first_unchecked(S, len);
+        if (i < 0) break;
+        S[i].state = ST_CHECKED;
+        c.st.global_steps++;
+        c.st.substeps++;
+        expand(&c, S[i].id, S, &len, c.st.substeps, 0);
+        len = order_and_cut(&c, S, len, L, c.st.substeps);
+    }
+    emit(S, len, k, ids, dists);
+    if (st) *st = c.st;
+    free(c.visited); free(S);
+    return 0;
+}
 
 int or_bfis(const float *base, int64_t n, int d, int64_t ld, int metric, const int32_t *adj, int R,
             int32_t entry_id, const float *q, int k, int L, int32_t *ids, float *dists, or_stats *st)
 {
-    problem P = {base, n, ld, d, metric, adj, R, q};
-    or_stats s = {0, 0, 0, 0, 0};
-    uint8_t *visited = (uint8_t *)calloc((size_t)n, 1);
-    entry *S = (entry *)malloc(sizeof(entry) * (size_t)(L + R));
-    if (!visited || !S) { free(visited); free(S); return -2; }
-    int64_t len = 0;
-
-    /* compute dist(P, Q) and add P into S */
-    S[len].dist = pdist(&P, entry_id); S[len].id = entry_id; S[len].state = ST_UNCHECKED; ++len;
-    visited[entry_id] = 1; s.dist_comps = 1;
-
-    for (;;) {
-        /* i <- index of the first unchecked vertex in S */
-        int64_t i = -1;
-        for (int64_t j = 0; j < len; ++j) if (S[j].state == ST_UNCHECKED) { i = j; break; }
-        if (i < 0) break;
-        S[i].state = ST_CHECKED;
-        s.expansions++; s.global_steps++; s.substeps++;
-        int32_t v = S[i].id;
-        for (int r = 0; r < R; ++r) {
-            int32_t u = adj[(int64_t)v * R + r];
-            if (u < 0) continue;
-            if (visited[u]) continue;
-            visited[u] = 1;
-            s.dist_comps++;
-            S[len].dist = pdist(&P, u); S[len].id = u; S[len].state = ST_UNCHECKED; ++len;
-        }
-        sort_entries(S, len);
-        if (len > L) len = L;
-    }
-    emit(S, len, k, ids, dists);
-    if (st) *st = s;
-    free(visited); free(S);
-    return 0;
+    const problem P = {base, n, ld, d, metric, adj, R, q};
+    return bfis_run(&P, NULL, entry_id, k, L, ids, dists, st);
 }
 
 /* ---------------------------------------------------------------- Top-M (Sec. 4.1) */
 
-/* Each step expands the first m unchecked candidates of S (all of them when fewer),
- * inserts the union of their unvisited neighbours and truncates S to L.  The
- * neighbours are visited in (expanded candidate order, adjacency slot) order.
- * staged: m = 1 at the first step and doubles every step up to M (Sec. 4.2, t = 1). */
-int or_topm(const float *base, int64_t n, int d, int64_t ld, int metric, const int32_t *adj, int R,
-            int32_t entry_id, const float *q, int k, int L, int M, int staged, int32_t *ids, float *dists,
-            or_stats *st)
+/* Each step expands the m best unchecked candidates together (all of them when there are
+ * fewer), adds the union of their new neighbours and keeps the L best.  The neighbours are
+ * taken in the order (candidate in list order, position in its row).  staged: m is 1 at
+ * the first step and doubles after every step up to M (Sec. 4.2 with t = 1). */
+static int topm_run(const problem *P, const tracer *tr, int32_t entry_id, int k, int L, int M, int staged,
+                    int32_t *ids, float *dists, or_stats *st)
 {
-    problem P = {base, n, ld, d, metric, adj, R, q};
-    or_stats s = {0, 0, 0, 0, 0};
-    uint8_t *visited = (uint8_t *)calloc((size_t)n, 1);
-    entry *S = (entry *)malloc(sizeof(entry) * (size_t)(L + (int64_t)M * R));
+    search_ctx c;
+    entry *S = (entry *)malloc(sizeof(entry) * (size_t)(L + (int64_t)M * P->R));
     int32_t *act = (int32_t *)malloc(sizeof(int32_t) * (size_t)M);
-    if (!visited || !S || !act) { free(visited); free(S); free(act); return -2; }
-    int64_t len = 0;
+    if (ctx_open(&c, P, tr) != 0 || !S || !act) { free(c.visited); free(S); free(act); return -2; }
+    int64_t len = put_start(&c, S, entry_id);
     int m = staged ? 1 : M;
-
-    S[len].dist = pdist(&P, entry_id); S[len].id = entry_id; S[len].state = ST_UNCHECKED; ++len;
-    visited[entry_id] = 1; s.dist_comps = 1;
-
     for (;;) {
         int na = 0;
         for (int64_t j = 0; j < len && na < m; ++j)
             if (S[j].state == ST_UNCHECKED) { S[j].state = ST_CHECKED; act[na++] = S[j].id; }
         if (na == 0) break;
-        s.expansions += na; s.global_steps++; s.substeps++; s.merges++;
-        for (int a = 0; a < na; ++a) {
-            int32_t v = act[a];
-            for (int r = 0; r < R; ++r) {
-                int32_t u = adj[(int64_t)v * R + r];
-                if (u < 0 || visited[u]) continue;
-                visited[u] = 1;
-                s.dist_comps++;
-                S[len].dist = pdist(&P, u); S[len].id = u; S[len].state = ST_UNCHECKED; ++len;
-            }
-        }
-        sort_entries(S, len);
-        if (len > L) len = L;
+        c.st.global_steps++;
+        c.st.substeps++;
+        c.st.merges++;
+        for (int a = 0; a < na; ++a) expand(&c, act[a], S, &len, c.st.substeps, a);
+        len = order_and_cut(&c, S, len, L, c.st.substeps);
         if (staged && m < M) m = (2 * m < M) ? 2 * m : M;
     }
     emit(S, len, k, ids, dists);
-    if (st) *st = s;
-    free(visited); free(S); free(act);
+    if (st) *st = c.st;
+    free(c.visited); free(S); free(act);
     return 0;
+}
+
+int or_topm(const float *base, int64_t n, int d, int64_t ld, int metric, const int32_t *adj, int R,
+            int32_t entry_id, const float *q, int k, int L, int M, int staged, int32_t *ids, float *dists,
+            or_stats *st)
+{
+    const problem P = {base, n, ld, d, metric, adj, R, q};
+    return topm_run(&P, NULL, entry_id, k, L, M, staged, ids, dists, st);
 }
 
 /* ---------------------------------------------------------------- Algorithm 3 */
@@ -285,164 +404,199 @@ static int check_metrics(const int32_t *U, int m, int L, double ratio)
     return mean >= (double)L * ratio;
 }
 
-/* T workers (the maximum expansion width); sync selects CheckMetrics:
- *   OR_SYNC_BSP       merge after every sub-step
- *   OR_SYNC_STATIC    merge after static_I sub-steps (static_I <= 0: only when every
- *                     local queue is exhausted, i.e. no synchronisation)
- *   OR_SYNC_ADAPTIVE  Algorithm 2 with position ratio rho
- * staged: the expansion width starts at 1 and doubles after every merge (Algorithm 3);
- * otherwise it is T from the start. */
+/* Whether the workers merge after the local step just taken, the local_steps-th of this
+ * global step: after every one (bsp), after static_I of them (static; static_I <= 0:
+ * never, so only when no worker has work left), or when CheckMetrics says so (adaptive). */
+static int merge_due(int sync, int static_I, double rho, const int32_t *U, int m, int L, int local_steps)
+{
+    if (sync == OR_SYNC_BSP) return 1;
+    if (sync == OR_SYNC_STATIC) return static_I > 0 && local_steps >= static_I;
+    return check_metrics(U, m, L, rho);
+}
+
+/* The start of a global step (a reading of how Algorithm 3 splits the work): the unchecked
+ * entries of S, in key order, are dealt to the m workers in turn, the j-th to worker
+ * j mod m.  Each worker's local list is a copy of S in which the entries dealt to the
+ * others are FOREIGN: they keep their places but that worker never expands them.  Returns
+ * the number of unchecked entries dealt. */
+static int64_t deal(const entry *S, int64_t len, int m, entry *LS, int64_t stride, int64_t *LSlen)
+{
+    int64_t dealt = 0;
+    for (int t = 0; t < m; ++t) LSlen[t] = len;
+    for (int64_t j = 0; j < len; ++j) {
+        const int owner = S[j].state == ST_UNCHECKED ? (int)(dealt++ % m) : -1;
+        for (int t = 0; t < m; ++t) {
+            entry e = S[j];
+            if (e.state == ST_UNCHECKED && owner != t) e.state = ST_FOREIGN;
+            LS[(int64_t)t * stride + j] = e;
+        }
+    }
+    return dealt;
+}
+
+/* One local step of one worker: it expands the first entry of its own list that it may
+ * expand, adds what it found and keeps the L best.  Returns its update position (Sec. 4.3:
+ * the 0-based place of the best entry this step added, after the cut), or L when it had
+ * nothing to expand or nothing it added stayed (readings). */
+static int32_t local_step(search_ctx *c, entry *list, int64_t *len, int L, int worker)
+{
+    const int64_t i = first_unchecked(list, *len);
+    if (i < 0) return L;
+    list[i].state = ST_CHECKED;
+    const int64_t before = *len;
+    const int64_t added = expand(c, list[i].id, list, len, c->st.substeps, worker);
+    if (added == 0) return L;
+    entry *fresh = (entry *)malloc(sizeof(entry) * (size_t)added);
+    memcpy(fresh, list + before, sizeof(entry) * (size_t)added);
+    *len = order_and_cut(c, list, *len, L, c->st.substeps);
+    int32_t U = L;
+    for (int64_t j = 0; j < *len && U == L; ++j)
+        for (int64_t x = 0; x < added; ++x)
+            if (fresh[x].id == list[j].id) { U = (int32_t)j; break; }
+    free(fresh);
+    return U;
+}
+
+/* The merge (Algorithm 3): S and the m local lists become one list with one entry per
+ * vertex, checked if any copy is (FOREIGN counts as unchecked), in key order, cut to L.
+ * all: room for every entry of S and of the lists.  Returns the new length of S. */
+static int64_t merge_into(search_ctx *c, entry *S, int64_t len, const entry *LS, int64_t stride,
+                          const int64_t *LSlen, int m, entry *all, int L)
+{
+    int64_t na = 0;
+    for (int64_t j = 0; j < len; ++j) all[na++] = S[j];
+    for (int t = 0; t < m; ++t)
+        for (int64_t j = 0; j < LSlen[t]; ++j) all[na++] = LS[(int64_t)t * stride + j];
+    sort_entries(all, na);
+    /* copies of one vertex carry one key, so they sit together */
+    int64_t nd = 0;
+    for (int64_t j = 0; j < na; ++j) {
+        const int checked = all[j].state == ST_CHECKED;
+        if (nd > 0 && all[nd - 1].id == all[j].id) {
+            if (checked) all[nd - 1].state = ST_CHECKED;
+            continue;
+        }
+        all[nd] = all[j];
+        all[nd].state = checked ? ST_CHECKED : ST_UNCHECKED;
+        ++nd;
+    }
+    note_gaps(c, all, nd, L, c->st.substeps);
+    const int64_t keep = nd > L ? L : nd;
+    memcpy(S, all, sizeof(entry) * (size_t)keep);
+    return keep;
+}
+
+/* Speed-ANN with T workers, run in lockstep: within a global step every worker with work
+ * takes one local step per round, in worker order, against one shared visited set, so that
+ * a vertex two workers reach in the same round goes to the lower worker (and, within a
+ * worker, the earlier row position).  After each round the schedule decides whether the
+ * workers merge; they also merge when none has work left.  staged: the number of active
+ * workers starts at 1 and doubles after each merge, up to T (Algorithm 3); otherwise it is
+ * T throughout.  max_substeps > 0 (not in the paper): when that many local steps have been
+ * taken in all, the global step in progress merges and the search ends (stats flag 1,
+ * return value 1). */
+static int speedann_run(const problem *P, const tracer *tr, int32_t entry_id, int k, int L, int T, int sync,
+                        int static_I, double rho, int staged, int max_substeps, int32_t *ids, float *dists,
+                        or_stats *st)
+{
+    search_ctx c;
+    const int64_t stride = L + P->R;
+    entry *S = (entry *)malloc(sizeof(entry) * (size_t)L);
+    entry *LS = (entry *)malloc(sizeof(entry) * (size_t)T * (size_t)stride);
+    int64_t *LSlen = (int64_t *)malloc(sizeof(int64_t) * (size_t)T);
+    int32_t *U = (int32_t *)malloc(sizeof(int32_t) * (size_t)T);
+    entry *all = (entry *)malloc(sizeof(entry) * (size_t)(T + 1) * (size_t)L);
+    if (ctx_open(&c, P, tr) != 0 || !S || !LS || !LSlen || !U || !all) {
+        free(c.visited); free(S); free(LS); free(LSlen); free(U); free(all);
+        return -2;
+    }
+    int64_t len = put_start(&c, S, entry_id);
+    int m = staged ? 1 : T;
+    int ended = 0;
+    while (!ended) {
+        if (deal(S, len, m, LS, stride, LSlen) == 0) break;
+        c.st.global_steps++;
+        int local_steps = 0;
+        for (;;) {
+            int busy = 0;
+            for (int t = 0; t < m && !busy; ++t) busy = first_unchecked(LS + (int64_t)t * stride, LSlen[t]) >= 0;
+            if (!busy) break;
+            if (max_substeps > 0 && c.st.substeps >= max_substeps) {
+                ended = 1;
+                c.st.flags |= 1;
+                break;
+            }
+            c.st.substeps++;
+            local_steps++;
+            for (int t = 0; t < m; ++t) U[t] = local_step(&c, LS + (int64_t)t * stride, &LSlen[t], L, t);
+            if (merge_due(sync, static_I, rho, U, m, L, local_steps)) break;
+        }
+        len = merge_into(&c, S, len, LS, stride, LSlen, m, all, L);
+        c.st.merges++;
+        if (staged && m < T) m = (2 * m < T) ? 2 * m : T;
+    }
+    emit(S, len, k, ids, dists);
+    if (st) *st = c.st;
+    free(c.visited); free(S); free(LS); free(LSlen); free(U); free(all);
+    return ended;
+}
+
 int or_speedann(const float *base, int64_t n, int d, int64_t ld, int metric, const int32_t *adj, int R,
                 int32_t entry_id, const float *q, int k, int L, int T, int sync, int static_I, double rho,
                 int staged, int max_substeps, int32_t *ids, float *dists, or_stats *st)
 {
-    problem P = {base, n, ld, d, metric, adj, R, q};
-    or_stats s = {0, 0, 0, 0, 0};
-    uint8_t *visited = (uint8_t *)calloc((size_t)n, 1);
-    entry *S = (entry *)malloc(sizeof(entry) * (size_t)L);
-    entry *LS = (entry *)malloc(sizeof(entry) * (size_t)T * (size_t)(L + R));
-    int64_t *LSlen = (int64_t *)malloc(sizeof(int64_t) * (size_t)T);
-    int32_t *U = (int32_t *)malloc(sizeof(int32_t) * (size_t)T);
-    entry *all = (entry *)malloc(sizeof(entry) * (size_t)(T + 1) * (size_t)L);
-    if (!visited || !S || !LS || !LSlen || !U || !all) {
-        free(visited); free(S); free(LS); free(LSlen); free(U); free(all);
-        return -2;
-    }
-    int rc = 0;
-    int64_t len = 0;
-    int m = staged ? 1 : T;
-
-    /* compute dist(P, Q); add P into S */
-    S[len].dist = pdist(&P, entry_id); S[len].id = entry_id; S[len].state = ST_UNCHECKED; ++len;
-    visited[entry_id] = 1; s.dist_comps = 1;
-
-    for (;;) {
-        /* divide all unchecked vertices from S into LS: the j-th unchecked entry goes to
-         * worker j mod m; each local queue is a copy of S */
-        int64_t nunchecked = 0;
-        for (int t = 0; t < m; ++t) LSlen[t] = len;
-        for (int64_t j = 0; j < len; ++j) {
-            int owner = -1;
-            if (S[j].state == ST_UNCHECKED) owner = (int)(nunchecked++ % m);
-            for (int t = 0; t < m; ++t) {
-                entry e = S[j];
-                if (e.state == ST_UNCHECKED && owner != t) e.state = ST_FOREIGN;
-                LS[(int64_t)t * (L + R) + j] = e;
-            }
-        }
-        /* all local queues empty of unchecked work: done */
-        if (nunchecked == 0) break;
-        s.global_steps++;
-
-        /* local best-first searches in lockstep until CheckMetrics asks for a merge or
-         * no worker has unchecked vertices left */
-        int sub_in_step = 0;
-        for (;;) {
-            int any = 0;
-            for (int t = 0; t < m; ++t) {
-                entry *Q = LS + (int64_t)t * (L + R);
-                for (int64_t j = 0; j < LSlen[t]; ++j) if (Q[j].state == ST_UNCHECKED) { any = 1; break; }
-            }
-            if (!any) break;
-            /* step limit (not part of the paper): merge, then stop */
-            if (max_substeps > 0 && s.substeps >= max_substeps) { rc = 1; break; }
-            s.substeps++; sub_in_step++;
-            for (int t = 0; t < m; ++t) {
-                entry *Q = LS + (int64_t)t * (L + R);
-                int64_t i = -1;
-                for (int64_t j = 0; j < LSlen[t]; ++j) if (Q[j].state == ST_UNCHECKED) { i = j; break; }
-                U[t] = L;
-                if (i < 0) continue;                     /* idle worker */
-                Q[i].state = ST_CHECKED;
-                s.expansions++;
-                int32_t v = Q[i].id;
-                int64_t before = LSlen[t];
-                for (int r = 0; r < R; ++r) {
-                    int32_t u = adj[(int64_t)v * R + r];
-                    if (u < 0 || visited[u]) continue;
-                    visited[u] = 1;
-                    s.dist_comps++;
-                    Q[LSlen[t]].dist = pdist(&P, u); Q[LSlen[t]].id = u; Q[LSlen[t]].state = ST_UNCHECKED;
-                    LSlen[t]++;
-                }
-                if (LSlen[t] > before) {
-                    /* the update position is the best position of a newly inserted
-                     * candidate after the queue is sorted and truncated */
-                    entry *newest = (entry *)malloc(sizeof(entry) * (size_t)(LSlen[t] - before));
-                    memcpy(newest, Q + before, sizeof(entry) * (size_t)(LSlen[t] - before));
-                    int64_t nnew = LSlen[t] - before;
-                    sort_entries(Q, LSlen[t]);
-                    if (LSlen[t] > L) LSlen[t] = L;
-                    for (int64_t j = 0; j < LSlen[t]; ++j) {
-                        int isnew = 0;
-                        for (int64_t x = 0; x < nnew; ++x) if (newest[x].id == Q[j].id) { isnew = 1; break; }
-                        if (isnew) { U[t] = (int32_t)j; break; }
-                    }
-                    free(newest);
-                }
-            }
-            int merge_now;
-            if (sync == OR_SYNC_BSP) merge_now = 1;
-            else if (sync == OR_SYNC_STATIC) merge_now = static_I > 0 && sub_in_step >= static_I;
-            else merge_now = check_metrics(U, m, L, rho);
-            if (merge_now) break;
-        }
-
-        /* merge LS into S: one entry per id, CHECKED if any copy is CHECKED */
-        int64_t na = 0;
-        for (int64_t j = 0; j < len; ++j) all[na++] = S[j];
-        for (int t = 0; t < m; ++t)
-            for (int64_t j = 0; j < LSlen[t]; ++j) all[na++] = LS[(int64_t)t * (L + R) + j];
-        sort_entries(all, na);
-        len = 0;
-        for (int64_t j = 0; j < na; ++j) {
-            int checked = all[j].state == ST_CHECKED;
-            if (len > 0 && S[len - 1].id == all[j].id) {
-                if (checked) S[len - 1].state = ST_CHECKED;
-                continue;
-            }
-            if (len == L) continue;      /* keep scanning only for duplicates of kept ids */
-            S[len].dist = all[j].dist; S[len].id = all[j].id;
-            S[len].state = checked ? ST_CHECKED : ST_UNCHECKED;
-            ++len;
-        }
-        s.merges++;
-        if (rc == 1) break;
-        if (staged && m < T) m = (2 * m < T) ? 2 * m : T;
-    }
-    emit(S, len, k, ids, dists);
-    if (st) *st = s;
-    free(visited); free(S); free(LS); free(LSlen); free(U); free(all);
-    return rc;
+    const problem P = {base, n, ld, d, metric, adj, R, q};
+    return speedann_run(&P, NULL, entry_id, k, L, T, sync, static_I, rho, staged, max_substeps, ids, dists, st);
 }
 
 /* ---------------------------------------------------------------- batch drivers */
 
 /* algo: 0 = Algorithm 1, 1 = Top-M, 2 = Algorithm 3.  One query per OpenMP iteration;
- * queries are independent, so the thread count changes nothing but the time. */
-int or_search_batch(int algo, const float *base, int64_t n, int d, int64_t ld, int metric,
-                    const int32_t *adj, int R, int32_t entry_id, const float *queries, int64_t nq,
-                    int64_t ldq, int k, int L, int M, int sync, int static_I, double rho, int staged,
-                    int max_substeps, int32_t *ids, float *dists, or_stats *stats)
+ * queries are independent, so the thread count changes nothing but the time.  traces
+ * (NULL: none) gets one or_trace per query, with cap_exp expansions (4 ints each) and
+ * cap_keys added entries per query in texp, tkd and tki. */
+int or_search_batch_traced(int algo, const float *base, int64_t n, int d, int64_t ld, int metric,
+                           const int32_t *adj, int R, int32_t entry_id, const float *queries, int64_t nq,
+                           int64_t ldq, int k, int L, int M, int sync, int static_I, double rho, int staged,
+                           int max_substeps, int32_t *ids, float *dists, or_stats *stats, or_trace *traces,
+                           int32_t *texp, float *tkd, int32_t *tki, int64_t cap_exp, int64_t cap_keys)
 {
     int rc_all = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : rc_all)
     for (int64_t qi = 0; qi < nq; ++qi) {
         or_stats s;
         int rc;
-        const float *q = row(queries, qi, ldq);
+        const problem P = {base, n, ld, d, metric, adj, R, row(queries, qi, ldq)};
+        tracer tr = {0};
+        if (traces) {
+            tr.t = traces + qi;
+            tr.exp = texp + qi * 4 * cap_exp;
+            tr.key_dist = tkd + qi * cap_keys;
+            tr.key_id = tki + qi * cap_keys;
+            tr.cap_exp = cap_exp;
+            tr.cap_keys = cap_keys;
+        }
         if (algo == 0)
-            rc = or_bfis(base, n, d, ld, metric, adj, R, entry_id, q, k, L, ids + qi * k, dists + qi * k, &s);
+            rc = bfis_run(&P, &tr, entry_id, k, L, ids + qi * k, dists + qi * k, &s);
         else if (algo == 1)
-            rc = or_topm(base, n, d, ld, metric, adj, R, entry_id, q, k, L, M, staged, ids + qi * k,
-                         dists + qi * k, &s);
+            rc = topm_run(&P, &tr, entry_id, k, L, M, staged, ids + qi * k, dists + qi * k, &s);
         else
-            rc = or_speedann(base, n, d, ld, metric, adj, R, entry_id, q, k, L, M, sync, static_I, rho,
-                             staged, max_substeps, ids + qi * k, dists + qi * k, &s);
+            rc = speedann_run(&P, &tr, entry_id, k, L, M, sync, static_I, rho, staged, max_substeps, ids + qi * k,
+                              dists + qi * k, &s);
         if (stats) stats[qi] = s;
         rc_all |= rc != 0 ? (rc < 0 ? 2 : 1) : 0;
     }
     return rc_all;
+}
+
+int or_search_batch(int algo, const float *base, int64_t n, int d, int64_t ld, int metric,
+                    const int32_t *adj, int R, int32_t entry_id, const float *queries, int64_t nq,
+                    int64_t ldq, int k, int L, int M, int sync, int static_I, double rho, int staged,
+                    int max_substeps, int32_t *ids, float *dists, or_stats *stats)
+{
+    return or_search_batch_traced(algo, base, n, d, ld, metric, adj, R, entry_id, queries, nq, ldq, k, L, M, sync,
+                                  static_I, rho, staged, max_substeps, ids, dists, stats, NULL, NULL, NULL, NULL, 0,
+                                  0);
 }
 
 /* ---------------------------------------------------------------- graph construction */

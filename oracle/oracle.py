@@ -22,13 +22,12 @@ SYNC_BSP, SYNC_STATIC, SYNC_ADAPTIVE = 0, 1, 2
 ALGO_BFIS, ALGO_TOPM, ALGO_SPEEDANN = 0, 1, 2
 
 
-class Stats(C.Structure):
-    _fields_ = [("global_steps", C.c_int64), ("substeps", C.c_int64), ("expansions", C.c_int64),
-                ("dist_comps", C.c_int64), ("merges", C.c_int64)]
-
-
 STATS_DTYPE = np.dtype([("global_steps", "<i8"), ("substeps", "<i8"), ("expansions", "<i8"),
-                        ("dist_comps", "<i8"), ("merges", "<i8")])
+                        ("dist_comps", "<i8"), ("merges", "<i8"), ("flags", "<i8")])
+# or_trace: the smallest relative gap between neighbouring keys a decision depended on,
+# where it was seen, and how many expansions / added entries were recorded
+TRACE_DTYPE = np.dtype([("min_gap", "<f8"), ("gap_step", "<i8"), ("gap_dist", "<f4", (2,)),
+                        ("gap_id", "<i4", (2,)), ("n_exp", "<i8"), ("n_keys", "<i8")])
 
 
 def build(force: bool = True) -> str:
@@ -64,6 +63,9 @@ def lib():
                                       i64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dbl, C.c_int, C.c_int,
                                       i32p, f32p, st]
         L.or_search_batch.restype = C.c_int
+        tr = np.ctypeslib.ndpointer(TRACE_DTYPE, flags="C_CONTIGUOUS")
+        L.or_search_batch_traced.argtypes = L.or_search_batch.argtypes + [tr, i32p, f32p, i32p, i64, i64]
+        L.or_search_batch_traced.restype = C.c_int
         L.or_medoid.argtypes = [f32p, i64, C.c_int, i64]
         L.or_medoid.restype = i64
         L.or_prune.argtypes = [f32p, i64, C.c_int, i64, C.c_int, i32p, C.c_int, C.c_int, C.c_int, i32p]
@@ -125,9 +127,10 @@ def knn_self(base, rows, k, metric="l2"):
 
 
 def search(algo, base, adj, entry, queries, k, L, M=1, metric="l2", sync="adaptive", static_I=0,
-           rho=0.8, staged=True, max_substeps=0):
+           rho=0.8, staged=True, max_substeps=0, trace=None):
     """Run one of the search algorithms for every query.  algo: "bfis" (Algorithm 1),
-    "topm" (Top-M, M fixed or staged) or "speedann" (Algorithm 3, lockstep)."""
+    "topm" (Top-M, M fixed or staged) or "speedann" (Algorithm 3, lockstep).
+    trace=(cap_exp, cap_keys): also return a Trace of every query (see oracle.c)."""
     base, queries = _f32(base), _f32(queries)
     adj = np.ascontiguousarray(adj, dtype=np.int32)
     n, d = base.shape
@@ -138,12 +141,29 @@ def search(algo, base, adj, entry, queries, k, L, M=1, metric="l2", sync="adapti
     ids = np.empty((nq, k), np.int32)
     dists = np.empty((nq, k), np.float32)
     stats = np.zeros(nq, STATS_DTYPE)
-    rc = lib().or_search_batch(a, base, n, d, d, _metric(metric), adj, R, int(entry), queries, nq, d, int(k),
-                               int(L), int(M), s, int(static_I), float(rho), int(bool(staged)),
-                               int(max_substeps), ids, dists, stats)
+    args = (a, base, n, d, d, _metric(metric), adj, R, int(entry), queries, nq, d, int(k), int(L), int(M), s,
+            int(static_I), float(rho), int(bool(staged)), int(max_substeps), ids, dists, stats)
+    if trace is None:
+        rc = lib().or_search_batch(*args)
+    else:
+        ce, ck = (int(x) for x in trace)
+        tr = Trace(np.zeros(nq, TRACE_DTYPE), np.zeros((nq, max(ce, 1), 4), np.int32),
+                   np.zeros((nq, max(ck, 1)), np.float32), np.zeros((nq, max(ck, 1)), np.int32))
+        rc = lib().or_search_batch_traced(*args, tr.summary, tr.expansions, tr.key_dist, tr.key_id, ce, ck)
     if rc & 2:
         raise MemoryError("oracle search: allocation failed")
-    return ids, dists, stats
+    return (ids, dists, stats) if trace is None else (ids, dists, stats, tr)
+
+
+class Trace:
+    """Per-query record of an oracle search: summary (TRACE_DTYPE: the smallest relative gap
+    between neighbouring keys of distinct vertices in any sorted list, within the places
+    that decide what is kept, the local step and keys where it was seen, and the counts),
+    expansions[q, i] = (local step, worker, vertex, entries added) and the added entries'
+    keys in order, each up to the capacity asked for."""
+
+    def __init__(self, summary, expansions, key_dist, key_id):
+        self.summary, self.expansions, self.key_dist, self.key_id = summary, expansions, key_dist, key_id
 
 
 def bfis(base, adj, entry, queries, k, L, metric="l2"):

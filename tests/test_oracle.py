@@ -81,6 +81,26 @@ def test_knn_exclude_self_and_padding():
     assert list(ids[0, 3:]) == [-1, -1] and np.isinf(dists[0, 3:]).all()
 
 
+def test_knn_self_ids_other_than_row_index():
+    # queries that are base rows listed in a permuted order: query i skips base row
+    # rows[i], not row i.  Integer data with many ties, so the (distance, id) order and
+    # the exclusion are both visible; brute force in numpy, row by row.
+    w = synth.integer_grid(300, 5, 1, hi=3)
+    rows = np.random.default_rng(11).permutation(300)[:40].astype(np.int32)
+    ids, dists = oracle.knn_self(w.base, rows, 12)
+    B = w.base.astype(np.int64)
+    for i, r in enumerate(rows):
+        D = ((B - B[r]) ** 2).sum(1).astype(np.float64)
+        D[r] = np.inf
+        order = np.lexsort((np.arange(300), D))[:12]
+        np.testing.assert_array_equal(ids[i], order)
+        np.testing.assert_array_equal(dists[i], D[order].astype(np.float32))
+    assert not (ids == rows[:, None]).any()
+    # the plain row-index exclusion would differ: row rows[i] (distance 0) is a neighbour of
+    # query i under it whenever rows[i] != i
+    assert (rows != np.arange(40)).sum() > 30
+
+
 def test_recall_definition():
     # Recall = |R' & R| / K, averaged over queries; padding never counts
     found = np.array([[1, 2, 3], [4, -1, -1]])
@@ -96,14 +116,15 @@ def test_line_graph_golden(case):
     c = next(x for x in g["cases"] if x["name"] == case)
     if c["algo"] == "speedann":
         ids, d, st = oracle.speedann(base, adj, g["entry"], q, g["k"], g["L"], c["T"], sync=c["sync"],
-                                     static_I=c.get("static_I", 0), rho=c["rho"], staged=c["staged"])
+                                     static_I=c.get("static_I", 0), rho=c["rho"], staged=c["staged"],
+                                     max_substeps=c.get("max_substeps", 0))
     elif c["algo"] == "topm":
         ids, d, st = oracle.topm(base, adj, g["entry"], q, g["k"], g["L"], c["T"], staged=c["staged"])
     else:
         ids, d, st = oracle.bfis(base, adj, g["entry"], q, g["k"], g["L"])
     assert ids[0].tolist() == c["ids"]
     assert d[0].tolist() == c["dists"]
-    for key in ("global_steps", "substeps", "expansions", "dist_comps", "merges"):
+    for key in ("global_steps", "substeps", "expansions", "dist_comps", "merges", "flags"):
         if key in c:
             assert int(st[key][0]) == c[key], key
 
@@ -474,3 +495,38 @@ def test_permuted_search_is_the_search_of_the_relabelled_graph():
     np.testing.assert_array_equal(np.where(i2 >= 0, perm[np.maximum(i2, 0)], -1), i1)
     np.testing.assert_array_equal(d2, d1)
     np.testing.assert_array_equal(s2["dist_comps"], s1["dist_comps"])
+
+
+# ------------------------------------------------------------------ trace
+
+def test_trace_lists_expansions_and_gaps():
+    # the line graph: the trace of Algorithm 1 lists its 7 expansions in order with the
+    # entries each added, and the smallest gap between neighbouring keys (distances are the
+    # squares of distinct integers, so the smallest relative gap is known by hand)
+    g, base, adj, q = line_case()
+    ids, d, st, tr = oracle.search("bfis", base, adj, g["entry"], q, g["k"], g["L"], trace=(16, 16))
+    ex = tr.expansions[0][: int(tr.summary["n_exp"][0])]
+    assert ex[:, 2].tolist() == [0, 1, 3, 7, 2, 6, 9]
+    assert ex[:, 0].tolist() == [1, 2, 3, 4, 5, 6, 7]
+    assert ex[:, 3].tolist() == [2, 2, 1, 0, 1, 1, 0]
+    nk = int(tr.summary["n_keys"][0])
+    assert nk == 7 and tr.key_id[0][:nk].tolist() == [1, 5, 2, 3, 7, 6, 9]
+    # sorted lists seen (first L + 1 places): [1,0,5], [3,2,1,0,5], [7,3,2,1,0], [7,6,3,2,1],
+    # [9,7,6,3]; neighbouring squared distances 81/100, 100/144, 49/64, 64/81, ..., 4/16, 16/25,
+    # 25/49 -> the smallest relative gap is (100 - 81) / 100 = 0.19 between 1 and 0
+    assert tr.summary["min_gap"][0] == pytest.approx(0.19)
+    assert sorted(tr.summary["gap_id"][0].tolist()) == [0, 1]
+
+
+def test_trace_flags_exact_ties_and_changes_nothing():
+    w = synth.integer_grid(400, 4, 20, hi=3)
+    adj, entry, _ = oracle.build_graph(w.base, 12, 8, "rng", do_repair=True)
+    for algo, M in (("bfis", 1), ("topm", 3), ("speedann", 4)):
+        a = oracle.search(algo, w.base, adj, entry, w.queries, 5, 24, M)
+        b = oracle.search(algo, w.base, adj, entry, w.queries, 5, 24, M, trace=(8, 8))
+        for x, y in zip(a, b[:3]):
+            np.testing.assert_array_equal(x, y)
+        # integer grid data are full of equal distances between distinct vertices
+        assert (b[3].summary["min_gap"] == 0.0).all()
+        # more expansions than the capacity: all counted, the first 8 kept
+        assert (b[3].summary["n_exp"] == b[2]["expansions"]).all()
