@@ -555,7 +555,7 @@ __device__ __forceinline__ void search_body(const KArgs &A)
     int m = A.staged ? 1 : M;
     int32_t pv = -1, pu = -1;   // vertex whose adjacency row is prefetched, and this lane's entry of it
 
-    // compute dist(P, Q), add P to S and mark it visited
+    // the start point: its distance, the list holding only it, and the visited set
     if (w == 0) {
         if (lane == 0) claim[0] = A.entry;
         __builtin_amdgcn_wave_barrier();
