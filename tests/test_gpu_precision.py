@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity
 from paper_2201_13007_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -66,12 +67,11 @@ def test_search_over_codes(B, deep, dtype, M):
     print(f"case: search deep-8k ip {dtype} M={M} L=64", flush=True)
     ix = B.Index(dev(w.base), dev(adj), entry, metric="ip", dtype=dtype)
     r = ix.search(dev(w.queries), 10, 64, M, stats=True, rho=0.9)
-    eids, ed, est = oracle.speedann(deq, adj, entry, w.queries, 10, 64, M, rho=0.9, metric="ip")
-    np.testing.assert_array_equal(host(r.ids), eids)
-    np.testing.assert_allclose(host(r.dists), ed, rtol=1e-5, atol=1e-6)
-    st = host(r.stats)
-    np.testing.assert_array_equal(st[:, 3], est["dist_comps"])
-    np.testing.assert_array_equal(st[:, 1], est["substeps"])
+    e = parity.oracle_search(deq, adj, entry, w.queries, 10, 64, M, rho=0.9, metric="ip")
+    acc = parity.compare((host(r.ids), host(r.dists), host(r.stats)), e, exact=False, base=deq, queries=w.queries,
+                         metric="ip", atol=1e-6, label=f"{dtype} M={M}")
+    if acc:
+        print(f"   {len(acc)} queries parted at a near tie: {acc[:10]}", flush=True)
 
 
 def test_search_over_codes_l2_integer(B):

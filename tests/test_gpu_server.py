@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity
 from paper_2201_13007_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -103,10 +104,10 @@ def test_server_matches_oracle_sample(B, deep):
     print("case: server vs oracle, 24 requests burst", flush=True)
     ids, dists, lat, wall = srv.replay(w.queries[:n], k[:n], L[:n], M[:n], np.zeros(n, np.int64))
     for i in range(n):
-        eids, ed, _ = oracle.speedann(w.base, adj, entry, w.queries[i:i + 1], int(k[i]), int(L[i]), int(M[i]),
-                                      metric="ip")
-        np.testing.assert_array_equal(ids[i, :k[i]], eids[0], err_msg=f"request {i}")
-        np.testing.assert_allclose(dists[i, :k[i]], ed[0], rtol=1e-5, atol=1e-6)
+        ki = int(k[i])
+        e = parity.oracle_search(w.base, adj, entry, w.queries[i:i + 1], ki, int(L[i]), int(M[i]), metric="ip")
+        parity.compare((ids[i:i + 1, :ki], dists[i:i + 1, :ki], None), e, exact=False, base=w.base,
+                       queries=w.queries[i:i + 1], metric="ip", atol=1e-6, label=f"request {i}")
     srv.close()
 
 
