@@ -101,53 +101,97 @@ def load_traffic(workload_key):
     return t
 
 
-def cpu_oracle(w, adj, entry, k, L, M, seconds, storage="f32 vectors", lockstep=None, skw=None):
-    """The oracle's search timed on the host cores over a growing prefix of the queries
-    until about `seconds` of CPU work.  lockstep=(M2, L2, sync keywords): also the one-thread
-    latency of the oracle at that point (Algorithm 3 with M2 workers, emulated in sequence)."""
+def lscpu_model():
+    """CPU model, sockets, cores and threads from lscpu (model name from /proc/cpuinfo if
+    lscpu is missing)."""
+    import subprocess
+    f = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for ln in out.splitlines():
+            key, _, v = ln.partition(":")
+            f[key.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    model = f.get("Model name", "")
+    if not model:
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+        except OSError:
+            pass
+    if f.get("Socket(s)"):
+        model += (f"; {f.get('Socket(s)')} socket(s) x {f.get('Core(s) per socket', '?')} cores x "
+                  f"{f.get('Thread(s) per core', '?')} threads, {f.get('CPU(s)', '?')} logical CPUs")
+    return model
+
+
+def cpu_oracle(w, base_h, adj_h, entry, perm, gt, gpu_ids, k, point, seconds, lat_queries=1000, bfis_L=None,
+               lockstep=None):
+    """The oracle timed on the host cores, on the index the GPU searches (renumbered, ids
+    mapped back), as a reported baseline.
+      point = (M, L, sync keywords): the GPU's timed operating point.  Throughput: Algorithm
+        3 in lockstep over a growing prefix of the queries, one query per OpenMP thread, until
+        about `seconds` of wall time; its ids are compared with the GPU's.  Latency: the first
+        lat_queries queries one at a time (one thread), host wall time.
+      bfis_L: Algorithm 1 at its own smallest swept L reaching the recall target (the
+        sweep's one-walker point): throughput on all cores over a prefix, recall@k of that
+        prefix, and one-thread latency as above.
+      lockstep = (M, L, sync keywords): the GPU's best batch-1 point, one-thread latency."""
     import oracle
-    skw = skw or SYNCS["adaptive"]
-    adj_h = adj.cpu().numpy()
+    M, L, skw = point
     nq = w.queries.shape[0]
     nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    done, t_cpu, bs = 0, 0.0, 64
-    while t_cpu < seconds and done < nq:
-        n1 = min(bs, nq - done)
-        s0 = time.perf_counter()
-        oracle.speedann(w.base, adj_h, entry, w.queries[done:done + n1], k, L, M, metric=w.metric, **skw)
-        t_cpu += time.perf_counter() - s0
-        done += n1
-        bs = min(bs * 2, 2048)
-    # one query at a time on one thread: the paper's latency measure, as percentiles
-    lat = []
-    for i in range(min(100, nq)):
-        s0 = time.perf_counter()
-        oracle.speedann(w.base, adj_h, entry, w.queries[i:i + 1], k, L, M, metric=w.metric, **skw)
-        lat.append((time.perf_counter() - s0) * 1e3)
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-    except OSError:
-        pass
-    cpu = {"value": round(done / t_cpu, 1), "unit": "queries/s", "cores": nthreads, "kind": "oracle",
-           "sample": f"first {done} of the {nq} queries, same graph, {storage}, M={M}, L={L}, schedule {skw}, "
-                     f"lockstep emulation of Algorithm 3 in plain C, one query per OpenMP thread",
-           "cpu_model": model,
-           "latency_p50_ms": round(float(np.percentile(lat, 50)), 4),
-           "latency_p99_ms": round(float(np.percentile(lat, 99)), 4),
-           "latency_sample": f"first {len(lat)} queries one at a time, one thread, host wall time"}
-    if lockstep is not None and (tuple(lockstep[:2]) != (M, L) or lockstep[2] != skw):
-        M2, L2, skw = lockstep
-        lat2 = []
-        for i in range(min(50, nq)):
+    back = (lambda ids: np.where(ids >= 0, perm[np.maximum(ids, 0)], -1)) if perm is not None else (lambda ids: ids)
+
+    def throughput(run, budget):
+        done, t, bs, outs = 0, 0.0, 256, []
+        while t < budget and done < nq:
+            n1 = min(bs, nq - done)
             s0 = time.perf_counter()
-            oracle.speedann(w.base, adj_h, entry, w.queries[i:i + 1], k, L2, M2, metric=w.metric, **skw)
-            lat2.append((time.perf_counter() - s0) * 1e3)
-        cpu["lockstep_point"] = {"M": int(M2), "L": int(L2), "sync": skw, "queries": len(lat2),
-                                 "latency_p50_ms": round(float(np.percentile(lat2, 50)), 4),
-                                 "latency_p99_ms": round(float(np.percentile(lat2, 99)), 4)}
-    log(f"cpu oracle: {cpu['value']} q/s on {nthreads} threads ({done} queries, {t_cpu:.1f}s)")
+            outs.append(run(w.queries[done:done + n1]))
+            t += time.perf_counter() - s0
+            done += n1
+            bs = min(bs * 2, 4096)
+        return done, t, back(np.concatenate(outs))
+
+    def latency(run, count):
+        count = min(count, nq)
+        lat = np.empty(count)
+        for i in range(count):
+            s0 = time.perf_counter()
+            run(w.queries[i:i + 1])
+            lat[i] = (time.perf_counter() - s0) * 1e3
+        return {"latency_p50_ms": round(float(np.percentile(lat, 50)), 4),
+                "latency_p99_ms": round(float(np.percentile(lat, 99)), 4), "latency_queries": int(count)}
+
+    def alg3(Mx, Lx, kw):
+        return lambda q: oracle.speedann(base_h, adj_h, entry, q, k, Lx, Mx, metric=w.metric, **kw)[0]
+
+    done, t, ids = throughput(alg3(M, L, skw), seconds)
+    same = float((ids == gpu_ids[:done]).all(1).mean())
+    cpu = {"value": round(done / t, 1), "unit": "queries/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"first {done} of the {nq} queries, the index the GPU searches (breadth-first renumbered), "
+                     f"f32 vectors, M={M}, L={L}, schedule {skw}: lockstep emulation of Algorithm 3 in plain C, "
+                     f"one query per OpenMP thread",
+           "cpu_model": lscpu_model(),
+           "ids_equal_gpu": same,
+           **latency(alg3(M, L, skw), lat_queries)}
+    cpu["latency_sample"] = f"first {cpu['latency_queries']} queries one at a time, one thread, host wall time"
+    if bfis_L:
+        run = lambda q: oracle.bfis(base_h, adj_h, entry, q, k, bfis_L, metric=w.metric)[0]
+        done_b, t_b, ids_b = throughput(run, seconds / 2)
+        cpu["bfis"] = {"algorithm": "Algorithm 1 (best-first search, one walker)", "L": int(bfis_L),
+                       "qps": round(done_b / t_b, 1), "queries": int(done_b),
+                       "recall@10": round(float(oracle.recall(ids_b, gt[:done_b], k).mean()), 5),
+                       **latency(run, lat_queries)}
+    if lockstep is not None and (tuple(lockstep[:2]) != (M, L) or lockstep[2] != skw):
+        M2, L2, kw2 = lockstep
+        cpu["lockstep_point"] = {"M": int(M2), "L": int(L2), "sync": kw2, **latency(alg3(M2, L2, kw2), lat_queries)}
+    log(f"cpu oracle: {cpu['value']} q/s on {nthreads} threads ({done} queries, {t:.1f}s), ids equal to the GPU's "
+        f"for {same:.4f} of them; one thread p50 {cpu['latency_p50_ms']} ms"
+        + (f"; Algorithm 1 at L={bfis_L}: {cpu['bfis']['qps']} q/s, p50 {cpu['bfis']['latency_p50_ms']} ms"
+           if bfis_L else ""))
     return cpu
 
 
@@ -267,7 +311,11 @@ def deep_main(args, torch, B, synth, dev):
                 "algorithmic_bytes_per_launch": round(bytes_launch),
                 "kernel_ms": round(float(launch_ms.mean()), 4),
                 "note": "search and re-rank launches timed together" if rr else "search launch"}
-    cpu = None if args.no_cpu else cpu_oracle(w, adj, entry, k, L32, M, args.cpu_seconds, skw=skw)
+    cpu = None
+    if not args.no_cpu:
+        r32 = index["f32"].search(queries, k, L32, M, **skw)
+        cpu = cpu_oracle(w, w.base, adj.cpu().numpy(), entry, None, gt.cpu().numpy(), r32.ids.cpu().numpy(), k,
+                         (M, L32, skw), args.cpu_seconds, args.cpu_latency_queries)
     res = {
         "metric": "QPS and recall@10 by vector storage (fp32 / bf16 / fp8-e4m3, exact fp32 re-rank), "
                   "distance error vs FP64, 1M×96 DEEP-shaped inner product, 1 GPU",
@@ -630,7 +678,9 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="base vectors (0: 1,000,000; 10,000,000 for serve)")
     ap.add_argument("--nq", type=int, default=0, help="queries (0: 10,000; 20,000 for gist)")
     ap.add_argument("--latency-queries", type=int, default=2000)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall time of the oracle's throughput leg (Algorithm 1's leg takes half of it)")
+    ap.add_argument("--cpu-latency-queries", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--M", type=int, default=0, help="time this walker count only (0: sweep)")
     ap.add_argument("--L", type=int, default=0, help="with --M, time this L (0: sweep)")
@@ -695,7 +745,6 @@ def main():
     torch.cuda.synchronize()
     log(f"ground truth in {time.time() - t0:.2f}s")
 
-    adj0, entry0 = adj, entry   # the original numbering, for the CPU oracle
     perm = None
     if args.order != "none":
         t0 = time.time()
@@ -866,8 +915,12 @@ def main():
                 "frac_of_gather_ceiling": round(achieved / gc["GBs"], 4)}
 
     # ---------------------------------------------------------------- CPU oracle baseline
-    cpu = None if args.no_cpu else cpu_oracle(w, adj0, entry0, k, L, M, args.cpu_seconds,
-                                              lockstep=(Mlat, Llat, SYNCS[sync_lat]), skw=SYNCS[SYNC])
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_oracle(w, base.cpu().numpy(), adj.cpu().numpy(), entry,
+                         perm.cpu().numpy() if perm is not None else None, gt.cpu().numpy(), r.ids.cpu().numpy(), k,
+                         (M, L, SYNCS[SYNC]), args.cpu_seconds, args.cpu_latency_queries,
+                         bfis_L=ops.get((1, "adaptive")), lockstep=(Mlat, Llat, SYNCS[sync_lat]))
 
     res = {
         "metric": "QPS and p50/p99 latency at recall@10=0.99, 1M×128 SIFT-shaped, 1 GPU",

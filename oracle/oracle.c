@@ -551,8 +551,9 @@ int or_speedann(const float *base, int64_t n, int d, int64_t ld, int metric, con
 
 /* ---------------------------------------------------------------- batch drivers */
 
-/* algo: 0 = Algorithm 1, 1 = Top-M, 2 = Algorithm 3.  One query per OpenMP iteration;
- * queries are independent, so the thread count changes nothing but the time.  traces
+/* algo: 0 = Algorithm 1, 1 = Top-M, 2 = Algorithm 3.  One query per OpenMP iteration (a
+ * single query runs on the calling thread alone); queries are independent, so the thread
+ * count changes nothing but the time.  traces
  * (NULL: none) gets one or_trace per query, with cap_exp expansions (4 ints each) and
  * cap_keys added entries per query in texp, tkd and tki. */
 int or_search_batch_traced(int algo, const float *base, int64_t n, int d, int64_t ld, int metric,
@@ -562,7 +563,7 @@ int or_search_batch_traced(int algo, const float *base, int64_t n, int d, int64_
                            int32_t *texp, float *tkd, int32_t *tki, int64_t cap_exp, int64_t cap_keys)
 {
     int rc_all = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(| : rc_all)
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : rc_all) if (nq > 1)
     for (int64_t qi = 0; qi < nq; ++qi) {
         or_stats s;
         int rc;
