@@ -342,8 +342,10 @@ int sa_gather_probe(const float *vec_dev, int64_t n, int32_t d, int64_t ld, int6
  * hardware queue of its own: GPU_MAX_HW_QUEUES, default 4).  sa_batch_run only
  * enqueues kernel launches and event records and waits, so it can be captured in a HIP
  * graph from hip_stream (the classes become parallel branches) and replayed.  The
- * workspace holds the uploaded per-query arrays and one visited-set region per query
- * (as sa_search sizes them for the class's largest L); the search regions are zero
+ * workspace holds the uploaded per-query arrays, two job counters per class (zero
+ * between runs) and one visited-set region per query (as sa_search sizes them for the
+ * class's largest L, for the largest of the LDS-table settings the tuner may choose; a
+ * persistent class uses one per resident workgroup); the search regions are zero
  * between runs.  A re-rank (params->rerank != 0) runs after each class's search, as in
  * sa_search, and needs the index's float32 vectors. */
 typedef struct sa_batch sa_batch;
@@ -368,16 +370,34 @@ int sa_batch_upload(const sa_batch *batch, void *workspace, size_t ws_bytes, voi
 int sa_batch_run(const sa_batch *batch, const float *queries_dev, int64_t ldq, int32_t *ids_dev, float *dists_dev,
                  int64_t ldo, sa_query_stats *stats_dev, void *workspace, size_t ws_bytes, void *hip_stream);
 
-/* Autotuner: times sa_batch_run (best of reps after one warm run) for 1, 2, 4 and 8
- * streams and, when a class has two or more walkers and params left lds_hash_slots at
- * 0, with and without LDS visited tables for those classes; keeps the fastest.  Results
+/* Autotuner (best of reps after one warm run each).  First every class alone, in each
+ * of its forms: one workgroup per query, or persistent (as many workgroups as the device
+ * holds at once, taking the class's queries from a device counter in the plan's order;
+ * not with a re-rank), each with each LDS visited-table setting sa_batch_class_options
+ * lists.  Then the whole batch on 1, 2, 4 and 8 streams for three plans: every class one
+ * workgroup per query, every class persistent, each class in its fastest form; the
+ * fastest plan and stream count are kept (sa_batch_describe reports every time).  Results
  * do not depend on the choice.  Synchronous; overwrites ids_dev and dists_dev. */
 int sa_batch_tune(sa_batch *batch, const float *queries_dev, int64_t ldq, int32_t *ids_dev, float *dists_dev,
                   int64_t ldo, void *workspace, size_t ws_bytes, int32_t reps, void *hip_stream);
 
 /* Sets the configuration by hand: streams 1, 2, 4 or 8; lds_hash_slots for the classes with
- * two or more walkers (as in sa_search_params). */
+ * two or more walkers (as in sa_search_params; it must give each such class the table one
+ * of its options gives). */
 int sa_batch_set_config(sa_batch *batch, int32_t streams, int32_t lds_hash_slots);
+
+/* Number of classes of the plan (in the order sa_batch_describe lists them). */
+int32_t sa_batch_classes(const sa_batch *batch);
+
+/* The settings class cls may run with: *count lds_hash_slots values (the first cap of them
+ * into lds_values), and whether the persistent form is allowed (no re-rank).  The
+ * workspace holds room for each of them. */
+int sa_batch_class_options(const sa_batch *batch, int32_t cls, int32_t *lds_values, int32_t cap, int32_t *count,
+                           int32_t *persistent_ok);
+
+/* Sets class cls by hand: an lds_hash_slots value that gives the table one of its options
+ * gives, and the persistent form (1) or one workgroup per query (0). */
+int sa_batch_set_class(sa_batch *batch, int32_t cls, int32_t lds_hash_slots, int32_t persistent);
 
 /* JSON description of the plan (classes, their sizes, configuration, last tuning) into
  * buf (NUL-terminated, truncated to len); returns the length it needs including the NUL,

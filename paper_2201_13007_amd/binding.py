@@ -22,7 +22,8 @@ QFLAG_MAX_STEPS, QFLAG_CAPACITY, QFLAG_SPILLED = 1, 2, 4
 EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_quantize", "sa_index_create_q", "sa_medoid", "sa_prune", "sa_reverse_edges",
            "sa_repair", "sa_build_graph", "sa_index_create", "sa_index_destroy", "sa_search_workspace_bytes", "sa_search",
            "sa_batch_create", "sa_batch_destroy", "sa_batch_workspace_bytes", "sa_batch_upload", "sa_batch_run",
-           "sa_batch_tune", "sa_batch_set_config", "sa_batch_describe", "sa_server_default_config",
+           "sa_batch_tune", "sa_batch_set_config", "sa_batch_classes", "sa_batch_class_options", "sa_batch_set_class",
+           "sa_batch_describe", "sa_server_default_config",
            "sa_server_create", "sa_server_destroy", "sa_server_submit", "sa_server_poll", "sa_server_replay",
            "sa_server_stats", "sa_graph_order", "sa_permute_rows", "sa_permute_graph", "sa_index_set_id_map",
            "sa_gather_probe", "sa_knn_last_rescanned", "sa_index_analyze", "sa_index_integer_range"]
@@ -92,6 +93,10 @@ def lib():
         L.sa_batch_run.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, sz, vp]
         L.sa_batch_tune.argtypes = [vp, vp, i64, vp, vp, i64, vp, sz, i32, vp]
         L.sa_batch_set_config.argtypes = [vp, i32, i32]
+        L.sa_batch_classes.argtypes = [vp]
+        L.sa_batch_classes.restype = i32
+        L.sa_batch_class_options.argtypes = [vp, i32, vp, i32, C.POINTER(i32), C.POINTER(i32)]
+        L.sa_batch_set_class.argtypes = [vp, i32, i32, i32]
         L.sa_batch_describe.argtypes = [vp, C.c_char_p, sz]
         L.sa_batch_describe.restype = i64
         L.sa_server_default_config.argtypes = [C.POINTER(ServerConfig)]
@@ -111,7 +116,8 @@ def lib():
         L.sa_gather_probe.argtypes = [vp, i64, i32, i64, i64, i32, C.c_uint32, vp, vp]
         for name in ("sa_knn", "sa_knn_ex", "sa_quantize", "sa_index_create_q", "sa_medoid", "sa_prune", "sa_reverse_edges", "sa_repair", "sa_build_graph", "sa_index_create",
                      "sa_search", "sa_batch_create", "sa_batch_upload", "sa_batch_run", "sa_batch_tune",
-                     "sa_batch_set_config", "sa_server_create", "sa_server_submit", "sa_server_replay",
+                     "sa_batch_set_config", "sa_batch_class_options", "sa_batch_set_class", "sa_server_create",
+                     "sa_server_submit", "sa_server_replay",
                      "sa_server_stats", "sa_graph_order", "sa_permute_rows", "sa_permute_graph",
                      "sa_index_set_id_map", "sa_gather_probe"):
             getattr(L, name).restype = C.c_int
@@ -438,6 +444,22 @@ class Batch:
 
     def set_config(self, streams: int, lds_hash_slots: int = 0):
         _check(lib().sa_batch_set_config(self._h, int(streams), int(lds_hash_slots)), "sa_batch_set_config")
+
+    def classes(self) -> int:
+        return int(lib().sa_batch_classes(self._h))
+
+    def class_options(self, cls: int):
+        """(lds_hash_slots settings class cls may take, whether it may run persistent)"""
+        import numpy as np
+        vals = np.zeros(8, np.int32)
+        cnt, pers = C.c_int32(), C.c_int32()
+        _check(lib().sa_batch_class_options(self._h, int(cls), vals.ctypes.data, 8, C.byref(cnt), C.byref(pers)),
+               "sa_batch_class_options")
+        return [int(v) for v in vals[:cnt.value]], bool(pers.value)
+
+    def set_class(self, cls: int, lds_hash_slots: int, persistent: bool):
+        _check(lib().sa_batch_set_class(self._h, int(cls), int(lds_hash_slots), int(bool(persistent))),
+               "sa_batch_set_class")
 
     def describe(self) -> dict:
         import json

@@ -95,7 +95,17 @@ struct SearchLaunch {
     // float32 vectors that are all integers in [int_lo, int_hi] with every exact partial
     // sum below 2^24 (int_lo > int_hi: not so); see index_integer_range
     int32_t int_lo = 1, int_hi = 0;
+    // persistent form (null: one workgroup per job): a resident grid of workgroups takes
+    // the nq jobs from this device counter pair (zero before the launch, zero after it);
+    // the workspace then needs one region per resident workgroup, at most nq.  Not with a
+    // re-rank (its lists stay in the regions of their jobs).
+    int32_t *jobctr = nullptr;
 };
+
+// Workgroups of kernel k (block threads, lds bytes of dynamic LDS) that the device can
+// hold at once, at most njobs: the grid of a persistent launch.  Cached per kernel,
+// LDS size and device.
+hipError_t resident_grid(const void *k, int block, uint32_t lds, int64_t njobs, int64_t *grid);
 
 // Whether every stored float32 coordinate is an integer such that, for d-dimensional
 // vectors and queries in the same range, every partial sum of a squared distance or

@@ -6,6 +6,9 @@
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace sa {
 namespace {
@@ -170,6 +173,32 @@ int index_integer_range(const float *x, int64_t n, int32_t d, int64_t ld, int32_
     return SA_OK;
 }
 
+hipError_t resident_grid(const void *k, int block, uint32_t lds, int64_t njobs, int64_t *grid)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, uint32_t, int>, int64_t> cache;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int64_t slots = 0;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find({k, lds, dev});
+        if (it != cache.end()) slots = it->second;
+    }
+    if (slots == 0) {
+        int per_cu = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, lds);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        slots = std::max<int64_t>(1, (int64_t)per_cu * cus);
+        std::lock_guard<std::mutex> g(mu);
+        cache[{k, lds, dev}] = slots;
+    }
+    *grid = std::max<int64_t>(1, std::min(njobs, slots));
+    return hipSuccess;
+}
+
 int launch_search(const SearchLaunch &a, hipStream_t stream)
 {
     int llog2, glog2, max_sub;
@@ -195,6 +224,9 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     A.codes = a.codes; A.scale = a.scale; A.ldc = a.ldc; A.vec32 = a.vec32; A.ld32 = a.ld32; A.rerank = a.p.rerank;
     A.adj = a.adj; A.queries = a.queries; A.ldq = a.ldq;
     A.qL = a.qL; A.qk = a.qk; A.order = a.order; A.ldo = a.ldo > 0 ? a.ldo : a.k;
+    if (a.jobctr && a.p.rerank != 0) return set_error(SA_EUNSUPPORTED, "the persistent form takes no re-rank");
+    if (a.nq > 0x7FFFFFFF) return set_error(SA_EINVAL, "nq=%lld out of range", (long long)a.nq);
+    A.jobctr = a.jobctr; A.njobs = (int32_t)a.nq;
     A.ids = a.ids; A.dists = a.dists; A.stats = a.stats;
     A.ghash = reinterpret_cast<unsigned long long *>(a.workspace);
     A.n = a.n;

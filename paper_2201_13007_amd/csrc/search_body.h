@@ -59,7 +59,7 @@ struct Ctrl {
     int32_t nslot;    // workspace-table slots written (zeroed again at the end)
     int32_t done;     // the search ended while one worker was active
     int32_t gsteps, substeps, merges, epoch;
-    int32_t pad;
+    int32_t job;      // persistent form: the job the workgroup runs next
 };
 
 struct KArgs {
@@ -90,7 +90,23 @@ struct KArgs {
     // runs (null: workgroup b runs query b)
     const int32_t *qL, *qk, *order;
     int64_t ldo;                 // row stride of ids and dists
+    // persistent form (null: one workgroup per job): jobctr[0] hands out the jobs 0 ..
+    // njobs - 1, jobctr[1] counts the workgroups that found none left; both are zero
+    // before a launch and the last workgroup sets them back to zero
+    int32_t *jobctr;
+    int32_t njobs;
 };
+
+// Persistent form, end of a workgroup (one thread): the last one to finish puts the job
+// counters back to zero for the next launch.
+__device__ __forceinline__ void release_jobs(int32_t *ctr)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (atomicAdd(ctr + 1, 1) == (int)gridDim.x - 1) {
+        atomicExch(ctr, 0);
+        atomicExch(ctr + 1, 0);
+    }
+}
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
@@ -494,13 +510,12 @@ __device__ void migrate_table(const unsigned long long *lh, int llog2, unsigned 
     }
 }
 
+// Job `job` runs query order[job] (or job) in workspace region `region`.
 template <int LPV, int NI, int DT>
-__device__ __forceinline__ void search_body(const KArgs &A)
+__device__ __forceinline__ void search_body(const KArgs &A, int64_t job, int64_t region)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6, nthr = blockDim.x;
-    // workgroup b runs query order[b] (or b) in workspace region b
-    const int64_t job = blockIdx.x;
     const int64_t qi = A.order ? A.order[job] : job;
     const int L = A.qL ? A.qL[qi] : A.L, M = A.M, R = A.R;
     const int kq = A.qk ? A.qk[qi] : A.k;
@@ -513,7 +528,7 @@ __device__ __forceinline__ void search_body(const KArgs &A)
     int32_t *const claim = reinterpret_cast<int32_t *>(smem + A.o_claim) + w * 64;
     Ctrl *const C = reinterpret_cast<Ctrl *>(smem + A.o_ctrl);
     unsigned long long *const lh = reinterpret_cast<unsigned long long *>(smem + A.o_hash);
-    unsigned long long *const gh = A.ghash ? A.ghash + ((size_t)job << (A.glog2 + 1)) : nullptr;
+    unsigned long long *const gh = A.ghash ? A.ghash + ((size_t)region << (A.glog2 + 1)) : nullptr;
     uint32_t *const gslots = gh ? reinterpret_cast<uint32_t *>(gh + (1ull << A.glog2)) : nullptr;
 
     const uint64_t t_start = __builtin_amdgcn_s_memrealtime();

@@ -8,16 +8,36 @@
 namespace sa {
 namespace search_detail {
 
+// workgroup b runs job b in workspace region b
 template <int LPV, int NI, int DT>
 __global__ void __launch_bounds__(1024) search_multi(KArgs A)
 {
-    search_body<LPV, NI, DT>(A);
+    search_body<LPV, NI, DT>(A, blockIdx.x, blockIdx.x);
+}
+
+// Persistent form: each resident workgroup takes jobs from the device counter until none
+// is left, every one in its own workspace region (see KArgs::jobctr).
+template <int LPV, int NI, int DT>
+__global__ void __launch_bounds__(1024) search_multi_loop(KArgs A)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    Ctrl *const C = reinterpret_cast<Ctrl *>(smem + A.o_ctrl);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) C->job = atomicAdd(A.jobctr, 1);
+        __syncthreads();
+        const int job = C->job;
+        if (job >= A.njobs) break;
+        search_body<LPV, NI, DT>(A, job, blockIdx.x);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) release_jobs(A.jobctr);
 }
 
 template <int LPV, int NI, int DT>
 hipError_t launch1(const KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t s)
 {
-    auto k = search_multi<LPV, NI, DT>;
+    auto k = A.jobctr ? search_multi_loop<LPV, NI, DT> : search_multi<LPV, NI, DT>;
     // the dynamic LDS limit is raised to the whole 160 KB once per instantiation and
     // device, not on every launch (the latency path launches one query at a time)
     static std::atomic<uint64_t> raised{0};
@@ -31,7 +51,12 @@ hipError_t launch1(const KArgs &A, int64_t nq, int M, uint32_t lds, hipStream_t 
         if (e != hipSuccess) return e;
         raised.fetch_or(bit, std::memory_order_acq_rel);
     }
-    hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64 * M), lds, s, A);
+    int64_t grid = nq;
+    if (A.jobctr) {
+        e = resident_grid(reinterpret_cast<const void *>(k), 64 * M, lds, nq, &grid);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64 * M), lds, s, A);
     return hipGetLastError();
 }
 

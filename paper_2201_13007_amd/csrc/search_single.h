@@ -256,8 +256,8 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
 
     const int lane = __lane_id();
     const int R = A.R, g2 = A.glog2;
-    const int L = A.qL ? A.qL[qi] : A.L;
-    const int kq = A.qk ? A.qk[qi] : A.k;
+    const int L = A.qL ? __builtin_amdgcn_readfirstlane(A.qL[qi]) : A.L;
+    const int kq = A.qk ? __builtin_amdgcn_readfirstlane(A.qk[qi]) : A.k;
     const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
     // the second half of the region: scratch while the table grows, and the list handed
     // to the re-rank kernel
@@ -450,11 +450,39 @@ __global__ void __launch_bounds__(64) search_single(KArgs A)
     single_query<LPV, NI, L2, DT, ACC32>(A, A.order ? A.order[job] : job, tbl);
 }
 
+// Persistent form: each resident workgroup takes jobs from the device counter until none
+// is left, every one in its own workspace region (see KArgs::jobctr).
+template <int LPV, int NI, bool L2, int DT, bool ACC32>
+__global__ void __launch_bounds__(64) search_single_loop(KArgs A)
+{
+    uint32_t *const tbl = reinterpret_cast<uint32_t *>(A.ghash) + ((size_t)blockIdx.x << (A.glog2 + 1));
+    for (;;) {
+        int job = 0;
+        if (__lane_id() == 0) job = atomicAdd(A.jobctr, 1);
+        job = __builtin_amdgcn_readfirstlane(job);
+        if (job >= A.njobs) break;
+        // (loads after stores are vector loads: made wave-uniform again, or everything
+        // derived from the query index would take vector registers)
+        const int32_t qi = A.order ? __builtin_amdgcn_readfirstlane(A.order[job]) : job;
+        single_query<LPV, NI, L2, DT, ACC32>(A, qi, tbl);
+    }
+    if (__lane_id() == 0) search_detail::release_jobs(A.jobctr);
+}
+
 template <int LPV, int NI, int DT, bool ACC32>
 hipError_t launch1(const KArgs &A, int64_t nq, hipStream_t s)
 {
-    auto k = A.metric == SA_L2 ? search_single<LPV, NI, true, DT, ACC32> : search_single<LPV, NI, false, DT, ACC32>;
     const uint32_t lds = single_lds_bytes<LPV>();
+    if (A.jobctr) {
+        auto k = A.metric == SA_L2 ? search_single_loop<LPV, NI, true, DT, ACC32>
+                                   : search_single_loop<LPV, NI, false, DT, ACC32>;
+        int64_t grid = nq;
+        const hipError_t e = resident_grid(reinterpret_cast<const void *>(k), 64, lds, nq, &grid);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64), lds, s, A);
+        return hipGetLastError();
+    }
+    auto k = A.metric == SA_L2 ? search_single<LPV, NI, true, DT, ACC32> : search_single<LPV, NI, false, DT, ACC32>;
     hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64), lds, s, A);
     return hipGetLastError();
 }

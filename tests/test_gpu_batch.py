@@ -81,9 +81,33 @@ def test_batch_equals_search_under_every_config(B, gist):
             r = bt.run(q)
             np.testing.assert_array_equal(host(r.ids), want_ids)
             np.testing.assert_array_equal(host(r.dists), want_d)
+    # every candidate the tuner may pick: each class in each of its LDS settings, in both
+    # forms (one workgroup per query, persistent), on one stream and on eight
+    opts = [bt.class_options(c) for c in range(bt.classes())]
+    assert all(o[1] for o in opts)
+    for persistent in (False, True):
+        for j in range(max(len(o[0]) for o in opts)):
+            for c, (vals, _) in enumerate(opts):
+                bt.set_class(c, vals[j % len(vals)], persistent)
+            for streams in (1, 8):
+                print(f"case: batch classes persistent={persistent} lds option {j} streams={streams}", flush=True)
+                bt.set_config(streams, 0)   # the stream count (and the default table, set again below)
+                for c, (vals, _) in enumerate(opts):
+                    bt.set_class(c, vals[j % len(vals)], persistent)
+                r = bt.run(q)
+                np.testing.assert_array_equal(host(r.ids), want_ids)
+                np.testing.assert_array_equal(host(r.dists), want_d)
+    with pytest.raises(B.SpeedAnnError, match="room"):
+        bt.set_class(0, 777, False)
     print("case: batch tune", flush=True)
     t = bt.tune(q, reps=1)
-    assert len(t["candidates"]) >= 4 and t["chosen"]["streams"] in (1, 2, 4, 8)
+    assert len(t["classes"]) == bt.classes()
+    for c, cands in enumerate(t["classes"]):
+        assert len(cands) == 2 * len(opts[c][0])
+        assert {(x["lds_hash_slots"], x["persistent"]) for x in cands} == {(v, p) for v in opts[c][0] for p in (0, 1)}
+    assert {x["plan"] for x in t["plans"]} == {"per_query", "persistent", "mixed"}
+    best = min(t["plans"], key=lambda x: x["ms"])
+    assert t["chosen"]["plan"] == best["plan"] and t["chosen"]["streams"] == best["streams"]
     r = bt.run(q)
     np.testing.assert_array_equal(host(r.ids), want_ids)
     d = bt.describe()
@@ -91,12 +115,17 @@ def test_batch_equals_search_under_every_config(B, gist):
     assert {c["M"] for c in d["classes"]} == set(M.tolist())
 
 
-def test_batch_graph_replay(B, gist):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_graph_replay(B, gist, persistent):
+    # persistent: every class takes its queries from a device counter, which the last
+    # workgroup of each launch sets back to zero; replays and eager runs must keep working
     w, adj, entry, L, k, M = gist
     ix = B.Index(dev(w.base), dev(adj), entry)
     q = dev(w.queries)
     bt = B.Batch(ix, L, k, M, rho=0.8)
     bt.set_config(4, 0)
+    for c in range(bt.classes()):
+        bt.set_class(c, bt.class_options(c)[0][0], persistent)
     eager = bt.run(q)
     e_ids, e_d = host(eager.ids), host(eager.dists)
     out = bt.outputs()
@@ -107,7 +136,7 @@ def test_batch_graph_replay(B, gist):
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
-    print("case: batch captured in a graph, 3 replays", flush=True)
+    print(f"case: batch captured in a graph, 3 replays, persistent={persistent}", flush=True)
     with torch.cuda.graph(g):
         bt.run(q, out=out)
     written = np.arange(e_ids.shape[1])[None, :] < k[:, None]   # row q gets its first k[q] entries
@@ -132,14 +161,21 @@ def test_batch_one_class_and_sift(B, sync):
     L = np.full(40, 96, np.int32)
     k = np.full(40, 10, np.int32)
     M = np.full(40, 2, np.int32)
-    print(f"case: batch sift-5000 one class M=2 L=96 {sync}", flush=True)
     ix = B.Index(dev(w.base), dev(adj), entry)
-    r = B.Batch(ix, L, k, M, sync=sync).run(dev(w.queries), stats=True)
+    bt = B.Batch(ix, L, k, M, sync=sync)
     eids, ed, est = oracle.speedann(w.base, adj, entry, w.queries, 10, 96, 2, sync=sync)
-    np.testing.assert_array_equal(host(r.ids), eids)
-    np.testing.assert_array_equal(host(r.dists), ed)   # integer data: exact
-    for j, name in enumerate(["global_steps", "substeps", "expansions", "dist_comps", "merges"]):
-        np.testing.assert_array_equal(host(r.stats)[:, j], est[name], err_msg=name)
+    vals, _ = bt.class_options(0)
+    # bsp: the packed wavefront (default) and, with an LDS table, one wavefront per walker
+    assert len(vals) >= 2
+    for lds in vals:
+        for persistent in (False, True):
+            print(f"case: batch sift-5000 one class M=2 L=96 {sync} lds={lds} persistent={persistent}", flush=True)
+            bt.set_class(0, lds, persistent)
+            r = bt.run(dev(w.queries), stats=True)
+            np.testing.assert_array_equal(host(r.ids), eids)
+            np.testing.assert_array_equal(host(r.dists), ed)   # integer data: exact
+            for j, name in enumerate(["global_steps", "substeps", "expansions", "dist_comps", "merges"]):
+                np.testing.assert_array_equal(host(r.stats)[:, j], est[name], err_msg=name)
 
 
 def test_batch_errors(B, gist):

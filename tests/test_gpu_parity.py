@@ -377,11 +377,13 @@ def test_search_golden_line(B):
         print(f"case: golden line {c['name']}", flush=True)
         ix = B.Index(dev(base), dev(adj), gl["entry"])
         r = ix.search(dev(q), gl["k"], gl["L"], c["T"], stats=True, sync=c["sync"], rho=c["rho"],
-                      staged=c["staged"], static_I=c.get("static_I", 0))
+                      staged=c["staged"], static_I=c.get("static_I", 0), max_substeps=c.get("max_substeps", 0))
         assert host(r.ids)[0].tolist() == c["ids"]
         assert host(r.dists)[0].tolist() == c["dists"]
         st = host(r.stats)[0]
         assert st[:5].tolist() == [c["global_steps"], c["substeps"], c["expansions"], c["dist_comps"], c["merges"]]
+        # the step-limit flag (SA_QFLAG_MAX_STEPS) where the trace sets the oracle's
+        assert bool(st[5] & 1) == bool(c.get("flags", 0)), st[5]
 
 
 def test_search_edge_cases(B):
