@@ -577,7 +577,7 @@ def gist_main(args, torch, B, synth, dev):
     desc = bt.describe()
     for c in desc["classes"]:
         log(f"class M={c['M']} slots/lane={c['slots_per_lane']} queries={c['queries']} L_max={c['L_max']} "
-            f"stream={c['stream']}")
+            f"stream={c['stream']} lds_hash_slots={c['lds_hash_slots']} persistent={c['persistent']}")
 
     # one run with counters: recall and the bytes of the roofline
     r = bt.run(queries, stats=True)

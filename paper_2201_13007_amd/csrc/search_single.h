@@ -14,7 +14,8 @@
 // many of them land below it and pulls its old entry with a cross-lane permute.
 //
 // Visited set.  Open addressing over 32-bit entries (id + 1; zero is empty) in the
-// query's workspace region, claimed with compare-and-swap.  The table in use is a prefix
+// query's workspace region, claimed with compare-and-swap; the first probe of a vertex
+// goes to the line of its id block (see block_slot).  The table in use is a prefix
 // of the region that doubles (rehashing the set) when it passes three quarters full.  An
 // LDS array of recently claimed or rejected ids sits in front of it: a neighbour found
 // there is visited and needs no compare-and-swap.  When the query ends it clears the
@@ -55,7 +56,6 @@ using search_detail::VecSrc;
 using search_detail::bpermute64;
 using search_detail::distances;
 using search_detail::rerank_list;
-using search_detail::hash_slot;
 using search_detail::lanemask_lt;
 using search_detail::low_bits;
 using search_detail::rdlane64;
@@ -187,11 +187,29 @@ __device__ __forceinline__ int insert_batch(Queue<NI> &Q, int L, uint64_t mk, ui
     return fmin;
 }
 
+// Slots of vertex u in a table of 2^t entries (t >= 6).  The first probe keeps the 32
+// vertices of one id block (u / 32) together in one 128-byte line, each at its own offset:
+// neighbours that a breadth-first numbering gave nearby ids then share lines, within a
+// step and from one step to the next, so a step's claims touch about half as many lines
+// and most of them are still in the L2 from the step before.  Later probes move by an odd
+// stride 32 r + 1 (r odd): a new line every time, and every slot of the table in turn.
+__device__ __forceinline__ uint32_t block_slot(uint32_t u, int t)
+{
+    return ((((u >> 5) * 2654435761u) >> (37 - t)) << 5) | (u & 31u);
+}
+
+__device__ __forceinline__ uint32_t block_stride(uint32_t u, int t)
+{
+    const uint32_t r = (((u ^ 0x9E3779B9u) * 2654435761u) >> (37 - t)) | 1u;
+    return ((r << 5) | 1u) & ((1u << t) - 1u);
+}
+
 // find or insert u; *fresh tells whether this call inserted it.  NO_SLOT: table full.
 __device__ __forceinline__ uint32_t claim(uint32_t *T, int log2cap, uint32_t u, bool *fresh)
 {
     const uint32_t mask = (1u << log2cap) - 1u;
-    uint32_t s = hash_slot(u, log2cap);
+    uint32_t s = block_slot(u, log2cap);
+    const uint32_t step = block_stride(u, log2cap);
     *fresh = false;
     for (uint32_t probe = 0; probe <= mask; ++probe) {
         const uint32_t old = atomicCAS(&T[s], 0u, u + 1u);
@@ -200,7 +218,7 @@ __device__ __forceinline__ uint32_t claim(uint32_t *T, int log2cap, uint32_t u, 
             return s;
         }
         if (old == u + 1u) return s;
-        s = (s + 1) & mask;
+        s = (s + step) & mask;
     }
     return NO_SLOT;
 }
