@@ -281,6 +281,21 @@ int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64
               int32_t M, const sa_search_params *params, int32_t *ids_dev, float *dists_dev,
               sa_query_stats *stats_dev, void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): sa_search with the same arguments
+ * except the workspace, which is a static 64 MiB device array of the library instead
+ * (every device the library runs on holds its own copy until the process ends).  Calls
+ * whose workspace would exceed it (sa_search_workspace_bytes > 64 MiB; e.g. L = 192,
+ * M = 2 takes 64 KB per query) are rejected with SA_ECAPACITY.  All calls on one device
+ * share that array, as sa_search calls that share a workspace do: calls that overlap
+ * on one device (other streams, other host threads) race and must not be made.  The
+ * first call on a device also enqueues, ahead of its search, a kernel that zero-fills the
+ * array (every search leaves it zero again).  Allocates nothing and calls no allocating
+ * routine; enqueued on hip_stream like sa_search. */
+int sa_search_noalloc(const sa_index *index, const float *queries_dev, int64_t nq, int64_t ldq, int32_t k,
+                      int32_t L, int32_t M, const sa_search_params *params, int32_t *ids_dev, float *dists_dev,
+                      sa_query_stats *stats_dev, void *hip_stream);
+
 /* ------------------------------------------------------------------ renumbering
  *
  * The GPU counterpart of the neighbour grouping of Sec. 4.4: renumber the vertices so

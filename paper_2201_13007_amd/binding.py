@@ -26,7 +26,8 @@ EXPORTS = ["sa_last_error", "sa_default_params", "sa_knn", "sa_knn_ex", "sa_quan
            "sa_batch_describe", "sa_server_default_config",
            "sa_server_create", "sa_server_destroy", "sa_server_submit", "sa_server_poll", "sa_server_replay",
            "sa_server_stats", "sa_graph_order", "sa_permute_rows", "sa_permute_graph", "sa_index_set_id_map",
-           "sa_gather_probe", "sa_knn_last_rescanned", "sa_index_analyze", "sa_index_integer_range"]
+           "sa_gather_probe", "sa_knn_last_rescanned", "sa_index_analyze", "sa_index_integer_range",
+           "sa_search_noalloc"]
 
 
 class SearchParams(C.Structure):
@@ -84,6 +85,7 @@ def lib():
         L.sa_search_workspace_bytes.argtypes = [vp, i64, i32, i32, i32, C.POINTER(SearchParams)]
         L.sa_search_workspace_bytes.restype = sz
         L.sa_search.argtypes = [vp, vp, i64, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp, sz, vp]
+        L.sa_search_noalloc.argtypes = [vp, vp, i64, i64, i32, i32, i32, C.POINTER(SearchParams), vp, vp, vp, vp]
         L.sa_batch_create.argtypes = [vp, i64, vp, vp, vp, C.POINTER(SearchParams), C.POINTER(vp)]
         L.sa_batch_destroy.argtypes = [vp]
         L.sa_batch_destroy.restype = None
@@ -115,7 +117,7 @@ def lib():
         L.sa_index_set_id_map.argtypes = [vp, vp]
         L.sa_gather_probe.argtypes = [vp, i64, i32, i64, i64, i32, C.c_uint32, vp, vp]
         for name in ("sa_knn", "sa_knn_ex", "sa_quantize", "sa_index_create_q", "sa_medoid", "sa_prune", "sa_reverse_edges", "sa_repair", "sa_build_graph", "sa_index_create",
-                     "sa_search", "sa_batch_create", "sa_batch_upload", "sa_batch_run", "sa_batch_tune",
+                     "sa_search", "sa_search_noalloc", "sa_batch_create", "sa_batch_upload", "sa_batch_run", "sa_batch_tune",
                      "sa_batch_set_config", "sa_batch_class_options", "sa_batch_set_class", "sa_server_create",
                      "sa_server_submit", "sa_server_replay",
                      "sa_server_stats", "sa_graph_order", "sa_permute_rows", "sa_permute_graph",
@@ -378,6 +380,25 @@ class Index:
         _check(lib().sa_search(self._h, queries.data_ptr(), nq, queries.stride(0), k, L, M, C.byref(params),
                                ids.data_ptr(), dists.data_ptr(), st.data_ptr() if st is not None else None,
                                ws.data_ptr(), ws.numel(), _stream(stream)), "sa_search")
+        return SearchResult(ids, dists, st)
+
+    def search_noalloc(self, queries: torch.Tensor, k: int, L: int, M: int = 1, out=None,
+                       params: SearchParams | None = None, stream=None, **kw) -> SearchResult:
+        """sa_search_noalloc: the search with the library's static device workspace.  The
+        library allocates nothing; with out=(ids, dists, stats or None) given, neither does
+        this call (queries must then be contiguous with d a multiple of 4)."""
+        if params is None:
+            params = make_params(**kw)
+        if out is None:
+            queries = pad_dim(_mat(queries, "queries"))
+            nq, dev = queries.shape[0], self.vec.device
+            out = (torch.empty((nq, k), dtype=torch.int32, device=dev),
+                   torch.empty((nq, k), dtype=torch.float32, device=dev), None)
+        ids, dists, st = out
+        nq = ids.shape[0]
+        _check(lib().sa_search_noalloc(self._h, queries.data_ptr(), nq, queries.stride(0), k, L, M, C.byref(params),
+                                       ids.data_ptr(), dists.data_ptr(), st.data_ptr() if st is not None else None,
+                                       _stream(stream)), "sa_search_noalloc")
         return SearchResult(ids, dists, st)
 
 

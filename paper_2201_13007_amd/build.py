@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspeedann.so")
 SOURCES = ["capi.hip", "search.hip", "search_single_f32.hip", "search_single_bf16.hip", "search_single_fp8.hip",
            "search_multi_f32.hip", "search_multi_bf16.hip", "search_multi_fp8.hip", "knn.hip", "knn_mfma.hip",
-           "graph.hip", "quant.hip", "rerank.hip", "batch.hip", "server.hip", "reorder.hip", "probe.hip"]
+           "graph.hip", "quant.hip", "rerank.hip", "batch.hip", "server.hip", "reorder.hip", "probe.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
