@@ -327,7 +327,7 @@ class Index:
                                            _metric(metric), adj.data_ptr(), adj.shape[1], self.entry, C.byref(h)),
                    "sa_index_create_q")
         self._h = h
-        self._ws = None
+        self._ws = {}   # stream handle -> workspace
         self._lib = lib()   # kept for __del__, which may run after module teardown
         if dtype == "f32" and analyze:
             _check(lib().sa_index_analyze(h, _stream(None)), "sa_index_analyze")
@@ -354,11 +354,20 @@ class Index:
     def workspace_bytes(self, nq, k, L, M, params: SearchParams) -> int:
         return int(lib().sa_search_workspace_bytes(self._h, nq, k, L, M, C.byref(params)))
 
-    def workspace(self, nbytes: int) -> torch.Tensor:
-        """Zero-filled device workspace; sa_search leaves it zero-filled."""
-        if self._ws is None or self._ws.numel() < nbytes:
-            self._ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=self.vec.device)
-        return self._ws
+    def workspace(self, nbytes: int, stream=None) -> torch.Tensor:
+        """Zero-filled device workspace of the searches on `stream` (default: the current
+        one); sa_search leaves it zero-filled.  One per stream, so that searches on
+        different streams never share one, allocated and zeroed on its stream: a buffer
+        replaced by a larger one goes back to torch's pool on the stream whose searches
+        used it, which reuses it only after them."""
+        s = stream if stream is not None else torch.cuda.current_stream()
+        key = int(s.cuda_stream)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            with torch.cuda.stream(s):
+                ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=self.vec.device)
+            self._ws[key] = ws
+        return ws
 
     def search(self, queries: torch.Tensor, k: int, L: int, M: int = 1, params: SearchParams | None = None,
                stats=False, stream=None, out=None, **kw) -> SearchResult:
@@ -376,7 +385,7 @@ class Index:
         else:
             ids, dists, st = out
         nbytes = self.workspace_bytes(nq, k, L, M, params)
-        ws = self.workspace(nbytes)
+        ws = self.workspace(nbytes, stream)
         _check(lib().sa_search(self._h, queries.data_ptr(), nq, queries.stride(0), k, L, M, C.byref(params),
                                ids.data_ptr(), dists.data_ptr(), st.data_ptr() if st is not None else None,
                                ws.data_ptr(), ws.numel(), _stream(stream)), "sa_search")

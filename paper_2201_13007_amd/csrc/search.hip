@@ -85,8 +85,12 @@ void resolve_params(const sa_search_params &in, int L, int M, int R, int &llog2,
         // three-quarter limit sits near 24 L, several times the 8 L or so a search visits
         // at these R; the general table keeps 64 L.  8 M R more cover the M R vertices one
         // local step may add on top.
-        int64_t want = (compact_table(M, llog2, in.sync, R) ? 32ll : 64ll) * L + 8ll * M * R;
-        if (want < 4096) want = 4096;
+        const bool compact = compact_table(M, llog2, in.sync, R);
+        int64_t want = (compact ? 32ll : 64ll) * L + 8ll * M * R;
+        // room to grow past the table a search starts in (at least 8192 and 24 L slots for
+        // one worker; 8192 for the general kernel): a rare query visits several times the
+        // usual 8-15 L vertices, and one that fills the region stops with a partial result
+        want = std::max<int64_t>(want, compact ? 2 * std::max<int64_t>(8192, 24ll * L) : 16384);
         // a re-rank takes the last 1025 entries of the slot list, beyond the three
         // quarters the search may fill: at least 8192 slots
         if (in.rerank != 0 && want < 8192) want = 8192;

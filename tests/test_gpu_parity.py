@@ -323,7 +323,7 @@ def test_search_single_table_growth(B, sift_setup, init):
     ix = B.Index(dev(w.base), dev(adj), entry)
     r = ix.search(dev(w.queries), 10, 100, 1, stats=True, ws_hash_init=init)
     torch.cuda.synchronize()
-    assert int(ix._ws.count_nonzero().item()) == 0
+    assert int(ix.workspace(0).count_nonzero().item()) == 0
     g = (host(r.ids), host(r.dists), host(r.stats))
     e = parity.oracle_search(w.base, adj, entry, w.queries, 10, 100, 1)
     assert_search_equal(g, e, exact=True, label=f"sift single growth init={init}")
@@ -355,7 +355,7 @@ def test_search_integer_data_two_passes(B, sift_setup):
         print(f"case: search sift-20k integer data, mixed queries, L={L}", flush=True)
         r = ix.search(dev(q), 10, L, 1, stats=True)
         torch.cuda.synchronize()
-        assert int(ix._ws.count_nonzero().item()) == 0
+        assert int(ix.workspace(0).count_nonzero().item()) == 0
         g = (host(r.ids), host(r.dists), host(r.stats))
         e = parity.oracle_search(w.base, adj, entry, q, 10, L, 1)
         assert_search_equal(g, e, exact=True, label=f"integer data mixed queries L={L}")
@@ -462,7 +462,7 @@ def test_workspace_stays_zero_and_reusable(B, sift_setup):
         print(f"case: workspace reuse L={L} M={M} lds={lds}", flush=True)
         r = ix.search(q, 10, L, M, stats=True, lds_hash_slots=lds)
         torch.cuda.synchronize()
-        assert int(ix._ws.count_nonzero().item()) == 0, f"workspace dirty after L={L} M={M}"
+        assert int(ix.workspace(0).count_nonzero().item()) == 0, f"workspace dirty after L={L} M={M}"
         eids, ed, est = oracle.speedann(w.base, adj, entry, w.queries, 10, L, M)
         np.testing.assert_array_equal(host(r.ids), eids)
         np.testing.assert_array_equal(host(r.stats)[:, 3], est["dist_comps"])
@@ -561,3 +561,25 @@ def test_gather_probe(B):
     with pytest.raises(B.SpeedAnnError, match="multiple of 4"):
         B._check(B.lib().sa_gather_probe(dev(w.base).data_ptr(), 20_000, 128, 128, 6, 64, 1, sink.data_ptr(), None),
                  "sa_gather_probe")
+
+
+def test_search_on_two_streams(B, sift_setup):
+    """Searches on two streams at once through one Index: each stream gets a workspace of
+    its own, so the results equal the ones on the default stream."""
+    w, adj, entry = sift_setup
+    ix = B.Index(dev(w.base), dev(adj), entry)
+    q = dev(w.queries)
+    want = [ix.search(q, 10, L, M, sync="bsp" if M == 2 else "adaptive") for L, M in ((192, 2), (96, 1))]
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    print("case: two streams, one index", flush=True)
+    with torch.cuda.stream(s1):
+        r1 = ix.search(q, 10, 192, 2, sync="bsp", stream=s1)
+    with torch.cuda.stream(s2):
+        r2 = ix.search(q, 10, 96, 1, stream=s2)
+    torch.cuda.synchronize()
+    assert ix.workspace(0, s1).data_ptr() != ix.workspace(0, s2).data_ptr()
+    np.testing.assert_array_equal(host(r1.ids), host(want[0].ids))
+    np.testing.assert_array_equal(host(r2.ids), host(want[1].ids))

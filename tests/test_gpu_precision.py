@@ -104,7 +104,7 @@ def test_rerank(B, deep, dtype, M, rr):
     np.testing.assert_array_equal(host(r.ids), eids)
     np.testing.assert_allclose(host(r.dists), ed, rtol=1e-5, atol=1e-6)
     # the workspace is zero again after the re-rank
-    assert int(ix._ws.count_nonzero().item()) == 0
+    assert int(ix.workspace(0).count_nonzero().item()) == 0
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
@@ -122,7 +122,7 @@ def test_rerank_after_table_growth(B, deep, dtype):
     eids, ed = oracle.rerank(w.base, w.queries, final, 10, metric="ip")
     np.testing.assert_array_equal(host(r.ids), eids)
     np.testing.assert_allclose(host(r.dists), ed, rtol=1e-5, atol=1e-6)
-    assert int(ix._ws.count_nonzero().item()) == 0
+    assert int(ix.workspace(0).count_nonzero().item()) == 0
 
 
 def test_rerank_needs_room_and_vectors(B, deep):

@@ -19,7 +19,7 @@ def test_noalloc_equals_search():
     adj, entry, _ = oracle.build_graph(w.base, 64, 32, "rng", do_repair=True)
     ix = B.Index(torch.from_numpy(w.base).cuda(), torch.from_numpy(adj).cuda(), entry)
     q_all = torch.from_numpy(w.queries).cuda()
-    for nq, L, M, sync in ((300, 192, 2, "bsp"), (37, 96, 1, "adaptive"), (300, 100, 4, "adaptive")):
+    for nq, L, M, sync in ((300, 192, 2, "bsp"), (37, 96, 1, "adaptive"), (200, 100, 4, "adaptive")):
         print(f"case: noalloc nq={nq} L={L} M={M} {sync}", flush=True)
         q = q_all[:nq].contiguous()
         want = ix.search(q, 10, L, M, stats=True, sync=sync)
