@@ -460,21 +460,8 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
 // longest first is scheduled longest first.  (A persistent loop over jobs in one
 // workgroup was measured: any loop around the search costs 17-36 more VGPRs, about a
 // third of the occupancy this latency-bound search lives on.)
-// Waves per SIMD the compiler is asked for: eight where that costs no scratch memory (the
-// scalar registers spill into vector-register lanes instead), which the compiler's
-// resource report shows for queues of one slot per lane, and of two or three with float32
-// accumulation or reduced-precision storage (bf16 at one lane per vector excepted);
-// elsewhere whatever the registers give.
-template <int LPV, int NI, int DT, bool ACC32>
-constexpr int waves_wanted()
-{
-    const bool fits = NI == 1 || (NI <= 3 && (ACC32 || DT == SA_FP8E4M3 || (DT == SA_BF16 && !(LPV == 1 && NI == 3))));
-    return fits ? 8 : 1;
-}
-
 template <int LPV, int NI, bool L2, int DT, bool ACC32>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_wanted<LPV, NI, DT, ACC32>(), 8)))
-search_single(KArgs A)
+__global__ void __launch_bounds__(64) search_single(KArgs A)
 {
     const int32_t job = blockIdx.x;
     uint32_t *const tbl = reinterpret_cast<uint32_t *>(A.ghash) + ((size_t)job << (A.glog2 + 1));
