@@ -144,12 +144,14 @@ __global__ void prune_kernel(const float *base, int64_t n, int d, int64_t ld, in
 
 // ---------------------------------------------------------------- repair helpers
 
-// key (distance to u, id) of the nearest vertex w with mask[w] and deg[w] < R
-__global__ void nearest_marked(const float *base, int64_t n, int d, int64_t ld, int metric, const uint8_t *mask,
-                               const int32_t *deg, int R, int32_t u, unsigned long long *result)
+// For several vertices at once: results[j] = the smallest key (distance to us[j], id)
+// over the marked vertices with a free slot (grid.y = j); results start as KEY_EMPTY
+__global__ void nearest_marked_batch(const float *base, int64_t n, int d, int64_t ld, int metric, const uint8_t *mask,
+                                     const int32_t *deg, int R, const int32_t *us, unsigned long long *results)
 {
     __shared__ unsigned long long sk[256];
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t u = us[blockIdx.y];
     unsigned long long key = KEY_EMPTY;
     if (w < n && mask[w] && deg[w] < R) {
         float dd = dist_seq(base + w * ld, base + (int64_t)u * ld, d, metric);
@@ -161,7 +163,13 @@ __global__ void nearest_marked(const float *base, int64_t n, int d, int64_t ld, 
         if (threadIdx.x < s && sk[threadIdx.x + s] < sk[threadIdx.x]) sk[threadIdx.x] = sk[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && sk[0] != KEY_EMPTY) atomicMin(result, sk[0]);
+    if (threadIdx.x == 0 && sk[0] != KEY_EMPTY) atomicMin(results + blockIdx.y, sk[0]);
+}
+
+__global__ void fill_u64_n(unsigned long long *p, int64_t cnt, unsigned long long v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) p[i] = v;
 }
 
 // distance of every edge p -> c, computed as d(c, p)
@@ -173,17 +181,6 @@ __global__ void edge_dists(const float *base, int64_t n, int d, int64_t ld, int 
     const int64_t p = e / R;
     const int32_t c = adj[e];
     out[e] = (c >= 0 && c < n) ? dist_seq(base + (int64_t)c * ld, base + p * ld, d, metric) : 0.f;
-}
-
-__global__ void set_marks(uint8_t *mask, const int32_t *list, int64_t cnt)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) mask[list[i]] = 1;
-}
-
-__global__ void fill_u64(unsigned long long *p, unsigned long long v)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 // host-side distance with the same arithmetic as dist_seq
@@ -525,35 +522,78 @@ int repair_device(const float *base, int64_t n, int d, int64_t ld, int metric, i
     int64_t first_unmarked = 0;
     while (first_unmarked < n && mark[first_unmarked]) ++first_unmarked;
     if (first_unmarked < n) {
+        // In id order, as one at a time, but the searches go out in windows of WIN vertices:
+        // one launch finds, for each, the nearest vertex with a free slot among those marked
+        // when the window starts; processing the window in order, each answer is corrected
+        // with the vertices marked since (the same distance arithmetic on the host), and
+        // found again alone if its vertex has no free slot left.  The edges are those the
+        // one-at-a-time loop adds.  A window ends early once many vertices were marked in it.
+        constexpr int WIN = 256;
+        constexpr size_t MAX_NEW = 4096;
         DevBuf<uint8_t> dmask;
-        DevBuf<int32_t> ddeg, dlist;
+        DevBuf<int32_t> ddeg, dus;
         DevBuf<unsigned long long> dres;
-        if (dmask.alloc(n) != hipSuccess || ddeg.alloc(n) != hipSuccess || dlist.alloc(n) != hipSuccess ||
-            dres.alloc(1) != hipSuccess)
+        if (dmask.alloc(n) != hipSuccess || ddeg.alloc(n) != hipSuccess || dus.alloc(WIN) != hipSuccess ||
+            dres.alloc(WIN) != hipSuccess)
             return set_error(SA_ENOMEM, "repair: device allocation failed");
-        SA_HIP(hipMemcpyAsync(dmask.p, mark.data(), n, hipMemcpyHostToDevice, s));
-        SA_HIP(hipMemcpyAsync(ddeg.p, deg.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-        for (int64_t u = first_unmarked; u < n; ++u) {
-            if (mark[u]) continue;
-            hipLaunchKernelGGL(fill_u64, dim3(1), dim3(64), 0, s, dres.p, (unsigned long long)KEY_EMPTY);
-            hipLaunchKernelGGL(nearest_marked, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, base, n, d, ld,
-                               metric, dmask.p, ddeg.p, R, (int32_t)u, dres.p);
+        std::vector<int32_t> us;
+        std::vector<unsigned long long> res(WIN);
+        std::vector<int32_t> since;   // vertices marked since the window's searches
+        // nearest marked vertex with a free slot for each of us, under the current marks and degrees
+        auto search = [&](const std::vector<int32_t> &q) -> int {
+            SA_HIP(hipMemcpyAsync(dmask.p, mark.data(), n, hipMemcpyHostToDevice, s));
+            SA_HIP(hipMemcpyAsync(ddeg.p, deg.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+            SA_HIP(hipMemcpyAsync(dus.p, q.data(), sizeof(int32_t) * q.size(), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(fill_u64_n, dim3(1), dim3(WIN), 0, s, dres.p, (int64_t)q.size(),
+                               (unsigned long long)KEY_EMPTY);
+            hipLaunchKernelGGL(nearest_marked_batch, dim3((unsigned)((n + 255) / 256), (unsigned)q.size()), dim3(256),
+                               0, s, base, n, d, ld, metric, dmask.p, ddeg.p, R, dus.p, dres.p);
             SA_HIP(hipGetLastError());
-            unsigned long long best;
-            SA_HIP(hipMemcpyAsync(&best, dres.p, sizeof(best), hipMemcpyDeviceToHost, s));
+            SA_HIP(hipMemcpyAsync(res.data(), dres.p, sizeof(unsigned long long) * q.size(), hipMemcpyDeviceToHost, s));
             SA_HIP(hipStreamSynchronize(s));
-            if (best == KEY_EMPTY) return set_error(SA_ECAPACITY, "repair: no reachable vertex has a free slot");
-            const int32_t r = key_id(best);
-            adj[(int64_t)r * R + deg[r]] = (int32_t)u;
-            deg[r]++;
-            SA_HIP(hipMemcpyAsync(ddeg.p + r, &deg[r], sizeof(int32_t), hipMemcpyHostToDevice, s));
-            ++added;
-            mark_from(adj, R, n, (int32_t)u, mark, newly);
-            SA_HIP(hipMemcpyAsync(dlist.p, newly.data(), sizeof(int32_t) * newly.size(), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(set_marks, dim3((unsigned)((newly.size() + 255) / 256)), dim3(256), 0, s, dmask.p,
-                               dlist.p, (int64_t)newly.size());
-            SA_HIP(hipGetLastError());
-            SA_HIP(hipStreamSynchronize(s));
+            return SA_OK;
+        };
+        int64_t next = first_unmarked;
+        while (next < n) {
+            us.clear();
+            for (int64_t u = next; u < n && (int)us.size() < WIN; ++u)
+                if (!mark[u]) us.push_back((int32_t)u);
+            if (us.empty()) break;
+            int rc = search(us);
+            if (rc != SA_OK) return rc;
+            since.clear();
+            next = (int64_t)us.back() + 1;
+            for (size_t j = 0; j < us.size(); ++j) {
+                const int32_t u = us[j];
+                if (mark[u]) continue;
+                if (since.size() > MAX_NEW) {   // many new candidates: search the rest of the window again
+                    next = u;
+                    break;
+                }
+                // the window's answer is the best over the vertices marked at its start; those
+                // that filled up since cannot be taken, and those marked since are candidates
+                unsigned long long best = res[j];
+                if (best != KEY_EMPTY && deg[key_id(best)] >= R) {
+                    const std::vector<unsigned long long> saved(res);
+                    if ((rc = search(std::vector<int32_t>{u})) != SA_OK) return rc;
+                    best = res[0];
+                    res = saved;
+                } else {
+                    for (int32_t w : since)
+                        if (deg[w] < R) {
+                            const unsigned long long k =
+                                make_key(host_dist(&X[(size_t)w * ld], &X[(size_t)u * ld], d, metric), w);
+                            if (k < best) best = k;
+                        }
+                }
+                if (best == KEY_EMPTY) return set_error(SA_ECAPACITY, "repair: no reachable vertex has a free slot");
+                const int32_t r = key_id(best);
+                adj[(int64_t)r * R + deg[r]] = u;
+                deg[r]++;
+                ++added;
+                mark_from(adj, R, n, u, mark, newly);
+                since.insert(since.end(), newly.begin(), newly.end());
+            }
         }
     }
     SA_HIP(hipMemcpyAsync(adj_dev, adj.data(), sizeof(int32_t) * adj.size(), hipMemcpyHostToDevice, s));

@@ -225,6 +225,37 @@ def test_repair(B):
     assert oracle.reachable(want, entry)[0] == w.base.shape[0]
 
 
+def leafy_graph(n_main=200, n_leaf=2800, R=4, seed=5):
+    """A ring of n_main vertices (one slot used of R) and n_leaf vertices that point into it
+    and that nothing points to: one weak component, every leaf unreachable until the
+    repair bridges it.  Integer coordinates in 2-d: many equal distances, ties by id."""
+    rng = np.random.default_rng(seed)
+    n = n_main + n_leaf
+    base = rng.integers(0, 40, size=(n, 2)).astype(np.float32)
+    order = rng.permutation(n)          # ring vertices and leaves interleaved in id order
+    main, leaves = order[:n_main], order[n_main:]
+    adj = np.full((n, R), -1, np.int32)
+    for i in range(n_main):
+        adj[main[i], 0] = main[(i + 1) % n_main]
+    for v in leaves:
+        adj[v, 0] = main[rng.integers(0, n_main)]
+    return base, adj, int(main[0])
+
+
+def test_repair_many_bridges(B):
+    # the windowed reachability step: thousands of bridges, sources that fill up, and
+    # bridged leaves that become the nearest free source of later ones
+    base, adj, entry = leafy_graph()
+    want = adj.copy()
+    wb, wc = oracle.repair(base, want, entry, keep_local=1)
+    print(f"case: repair leafy graph n={base.shape[0]} bridges={wb} comps={wc}", flush=True)
+    assert wc == 1 and wb > 1000
+    g = dev(adj)
+    gb, gc = B.repair(dev(base), g, entry, keep_local=1)
+    np.testing.assert_array_equal(host(g), want)
+    assert (gb, gc) == (wb, wc)
+
+
 def test_build_graph_tiny(B):
     w = synth.tiny()
     print("case: build_graph tiny (16-NN, no repair)", flush=True)
