@@ -171,8 +171,9 @@ def cpu_oracle(w, base_h, adj_h, entry, perm, gt, gpu_ids, k, point, seconds, la
     done, t, ids = throughput(alg3(M, L, skw), seconds)
     same = float((ids == gpu_ids[:done]).all(1).mean())
     cpu = {"value": round(done / t, 1), "unit": "queries/s", "cores": nthreads, "kind": "oracle",
-           "sample": f"first {done} of the {nq} queries, the index the GPU searches (breadth-first renumbered), "
-                     f"f32 vectors, M={M}, L={L}, schedule {skw}: lockstep emulation of Algorithm 3 in plain C, "
+           "sample": f"first {done} of the {nq} queries, the index the GPU searches"
+                     + (" (renumbered, ids mapped back)" if perm is not None else "")
+                     + f", f32 vectors, M={M}, L={L}, schedule {skw}: lockstep emulation of Algorithm 3 in plain C, "
                      f"one query per OpenMP thread",
            "cpu_model": lscpu_model(),
            "ids_equal_gpu": same,
