@@ -286,7 +286,7 @@ int sa_search(const sa_index *index, const float *queries_dev, int64_t nq, int64
  * except the workspace, which is a static 64 MiB device array of the library instead
  * (every device the library runs on holds its own copy until the process ends).  Calls
  * whose workspace would exceed it (sa_search_workspace_bytes > 64 MiB; e.g. L = 192,
- * M = 2 takes 128 KB per query) are rejected with SA_ECAPACITY.  All calls on one device
+ * M = 2 takes 64 KB per query) are rejected with SA_ECAPACITY.  All calls on one device
  * share that array, as sa_search calls that share a workspace do: calls that overlap
  * on one device (other streams, other host threads) race and must not be made.  The
  * first call on a device also enqueues, ahead of its search, a kernel that zero-fills the

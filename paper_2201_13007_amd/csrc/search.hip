@@ -87,10 +87,10 @@ void resolve_params(const sa_search_params &in, int L, int M, int R, int &llog2,
         // local step may add on top.
         const bool compact = compact_table(M, llog2, in.sync, R);
         int64_t want = (compact ? 32ll : 64ll) * L + 8ll * M * R;
-        // room to grow past the table a search starts in (at least 8192 and 24 L slots for
-        // one worker; 8192 for the general kernel): a rare query visits several times the
-        // usual 8-15 L vertices, and one that fills the region stops with a partial result
-        want = std::max<int64_t>(want, compact ? 2 * std::max<int64_t>(8192, 24ll * L) : 16384);
+        // at least 8192 slots (16384 for eight or more workers, which explore more before they
+        // merge): at small L a rare query visits several times the usual 8-15 L vertices, and
+        // one that fills its region stops with a partial result
+        want = std::max<int64_t>(want, !compact && M >= 8 ? 16384 : 8192);
         // a re-rank takes the last 1025 entries of the slot list, beyond the three
         // quarters the search may fill: at least 8192 slots
         if (in.rerank != 0 && want < 8192) want = 8192;
