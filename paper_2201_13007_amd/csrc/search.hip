@@ -234,6 +234,8 @@ int launch_search(const SearchLaunch &a, hipStream_t stream)
     A.ids = a.ids; A.dists = a.dists; A.stats = a.stats;
     A.ghash = reinterpret_cast<unsigned long long *>(a.workspace);
     A.n = a.n;
+    A.idbits = 1;
+    while ((int64_t(1) << A.idbits) < a.n) ++A.idbits;
     A.d = a.d; A.metric = a.metric; A.R = a.R; A.entry = a.entry; A.k = a.k; A.L = a.L; A.M = a.M;
     A.sync = a.p.sync; A.static_I = a.p.static_I; A.staged = a.p.staged ? 1 : 0; A.max_substeps = max_sub;
     A.rho = a.p.rho; A.glog2 = glog2; A.llog2 = llog2;

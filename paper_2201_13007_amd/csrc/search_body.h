@@ -85,6 +85,7 @@ struct KArgs {
     // index_integer_range): pass 1 takes the queries that are integers in that range and
     // accumulates in float32, pass 0 takes the others; -1: one pass takes every query
     int32_t int_lo, int_hi, acc_pass;
+    int32_t idbits;              // vertex ids fit in idbits bits (2^idbits >= n)
     uint32_t o_skey, o_srank, o_schk, o_pub, o_newkey, o_claim, o_ctrl, o_hash, o_q;
     // batches: per-query L and k (null: L and k above) and the query each workgroup
     // runs (null: workgroup b runs query b)

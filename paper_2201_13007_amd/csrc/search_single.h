@@ -17,8 +17,8 @@
 // query's workspace region, claimed with compare-and-swap; the first probe of a vertex
 // goes to the line of its id block (see block_slot).  The table in use is a prefix
 // of the region that doubles (rehashing the set) when it passes three quarters full.  An
-// LDS array of recently claimed or rejected ids sits in front of it: a neighbour found
-// there is visited and needs no compare-and-swap.  When the query ends it clears the
+// LDS filter of recently claimed or rejected ids (two per set, exact 16-bit tags) sits in
+// front of it: a neighbour found there is visited and needs no compare-and-swap.  When the query ends it clears the
 // table in use with whole-line stores, which leaves the region zero for the next launch:
 // clearing only the slots it filled would write each of their lines back a second time
 // (they are long evicted by then), and listing them would cost writes of its own.
@@ -36,9 +36,9 @@ namespace single_detail {
 using search_detail::KArgs;
 using search_detail::NO_SLOT;
 
-// log2 of the entries of the per-query LDS filter of recently seen vertices: the largest
-// (up to 1024 entries, 4 KB) that keeps a wavefront's LDS within 160 KB / 28, so that LDS
-// never holds a CU below the 28 wavefronts the registers allow
+// log2 of the sets of the per-query LDS filter of recently seen vertices (two 16-bit tags
+// per 32-bit set): the largest (up to 1024 sets, 4 KB) that keeps a wavefront's LDS within
+// 160 KB / 28, so that LDS never holds a CU below the 28 wavefronts the registers allow
 template <int LPV>
 constexpr int seen_log2()
 {
@@ -266,11 +266,24 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
     uint64_t *const nkey = reinterpret_cast<uint64_t *>(smem);    // [64] keys of new vertices
     int32_t *const sid = reinterpret_cast<int32_t *>(nkey + 64);   // [64] their ids
     float *const qs = reinterpret_cast<float *>(sid + 64);          // [16 LPV] the query
-    // [SEEN] ids + 1 of recently claimed or rejected vertices, direct mapped: a vertex found
-    // here is visited and needs no compare-and-swap in the workspace table
+    // [SEEN] sets of recently claimed or rejected vertices: a vertex found here is visited and
+    // needs no compare-and-swap in the workspace table.  A vertex's id u is mapped by
+    // h = u * K_B mod 2^B, with K_B the odd number nearest 2^B / golden ratio (Fibonacci
+    // hashing at B bits: one-to-one on ids of B bits, and ids close together land in sets far
+    // apart); the top SEEN_LOG2 bits of h pick the set and the other tb = B - SEEN_LOG2 bits
+    // are the tag, so a tag names one vertex exactly.  A set's word holds a count of valid
+    // tags in its top two bits and up to W = min(3, 30 / tb) tags below, newest lowest; a new
+    // tag pushes the oldest out.  (Ids of more than 15 + SEEN_LOG2 bits: no filter.)
     uint32_t *const seen = reinterpret_cast<uint32_t *>(qs + 16 * LPV);
     constexpr int SEEN_LOG2 = seen_log2<LPV>();
     constexpr int SEEN = 1 << SEEN_LOG2;
+    const int hbits = A.idbits > SEEN_LOG2 ? A.idbits : SEEN_LOG2 + 1;
+    const int tbits = hbits - SEEN_LOG2;
+    const bool filter = tbits <= 15;
+    const uint32_t hmul = (2654435769u >> (32 - hbits)) | 1u;
+    const uint32_t tmask = (1u << tbits) - 1u;
+    const uint32_t ways = tbits <= 10 ? 3u : 2u;
+    const uint32_t tagbits = filter ? (1u << (ways * tbits)) - 1u : 0u;
 
     const int lane = __lane_id();
     const int R = A.R, g2 = A.glog2;
@@ -379,10 +392,15 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             pu = adj_lane[(int64_t)(second ? pv2 : pv) * R];
             if (aidx >= R || vl < 0 || u < 0 || u >= n) u = -1;   // idle walker, padding, malformed entries
             bool fresh = false;
-            const uint32_t hs = ((uint32_t)u * 2654435761u) >> (32 - SEEN_LOG2);
-            const bool ask = u >= 0 && seen[hs] != (uint32_t)u + 1u;
+            const uint32_t h = ((uint32_t)u * hmul) & (0xFFFFFFFFu >> (32 - hbits));
+            const uint32_t hs = h >> tbits, tag = h & tmask;
+            const uint32_t sw = u >= 0 && filter ? seen[hs] : 0u;
+            const uint32_t cnt = sw >> 30;
+            const bool known = (cnt > 0u && (sw & tmask) == tag) || (cnt > 1u && ((sw >> tbits) & tmask) == tag) ||
+                               (cnt > 2u && ((sw >> (2 * tbits)) & tmask) == tag);
+            const bool ask = u >= 0 && !known;
             if (ask) (void)claim(tbl, t2, (uint32_t)u, &fresh);
-            if (ask) seen[hs] = (uint32_t)u + 1u;
+            if (ask && filter) seen[hs] = (min(cnt + 1u, ways) << 30) | (((sw << tbits) | tag) & tagbits);
             const uint64_t fm = __ballot(fresh);
             const int nnew = __popcll(fm);
             if (fresh) sid[__popcll(fm & lanemask_lt())] = u;
