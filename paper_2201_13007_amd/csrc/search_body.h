@@ -266,12 +266,13 @@ __device__ __forceinline__ Raw4<DT> load_raw4(const VecSrc &V, int32_t id, int c
 // over arrays: the same steps as a per-vector helper cost some twenty more registers.)
 // ACC32: accumulate in float32 (only where every partial sum is an integer below 2^24, so
 // that the float32 sum is exact and equals the double one)
-template <int LPV, bool L2, int DT, bool ACC32 = false>
+// PB: vectors per lane group in one pass (PB 64 / LPV a pass, each pass one memory round
+// trip; each more in flight costs sixteen registers at d = 128)
+template <int LPV, bool L2, int DT, bool ACC32 = false, int PB = 1>
 __device__ __forceinline__ void distances(const VecSrc &V, int d, const float *qs, const int32_t *ids, int n,
                                           uint64_t *out)
 {
     constexpr int VPW = 64 / LPV;
-    constexpr int PB = 1;   // more vectors in flight cost two registers each (d = 128)
     const int lane = __lane_id(), grp = lane / LPV, g = lane % LPV;
     const int nch = d >> 2;
     for (int p0 = 0; p0 < n; p0 += VPW * PB) {

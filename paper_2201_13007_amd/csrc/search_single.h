@@ -16,10 +16,10 @@
 // Visited set.  Open addressing over 32-bit entries (id + 1; zero is empty) in the
 // query's workspace region, claimed with compare-and-swap; the first probe of a vertex
 // goes to the line of its id block (see block_slot).  The table in use is a prefix
-// of the region that doubles (rehashing the set) when it passes three quarters full.  An
-// LDS filter of recently claimed or rejected ids (two per set, exact 16-bit tags) sits in
-// front of it: a neighbour found there is visited and needs no compare-and-swap.  When the query ends it clears the
-// table in use with whole-line stores, which leaves the region zero for the next launch:
+// of the region that doubles (rehashing the set) when it passes three quarters full.  A
+// set-associative LDS filter of recently claimed or rejected ids (exact tags) sits in
+// front of it: a neighbour found there is visited and needs no compare-and-swap.  When
+// the query ends it clears the table in use with whole-line stores, which leaves the region zero for the next launch:
 // clearing only the slots it filled would write each of their lines back a second time
 // (they are long evicted by then), and listing them would cost writes of its own.
 //
@@ -36,8 +36,8 @@ namespace single_detail {
 using search_detail::KArgs;
 using search_detail::NO_SLOT;
 
-// log2 of the sets of the per-query LDS filter of recently seen vertices (two 16-bit tags
-// per 32-bit set): the largest (up to 1024 sets, 4 KB) that keeps a wavefront's LDS within
+// log2 of the sets of the per-query LDS filter of recently seen vertices (one 32-bit word
+// per set): the largest (up to 1024 sets, 4 KB) that keeps a wavefront's LDS within
 // 160 KB / 28, so that LDS never holds a CU below the 28 wavefronts the registers allow
 template <int LPV>
 constexpr int seen_log2()
@@ -348,6 +348,13 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
     // expansions' new vertices inserted, so one queue serves.  Walker 0 expands the first
     // unchecked entry on lanes 0-31, walker 1 the second on lanes 32-63.
     const bool two = A.M == 2;
+    // Two vectors per lane group in each pass of the distance loop (one round trip for 16
+    // new vertices at d = 128 instead of two) where that pays for its sixteen registers:
+    // float32 rows with up to three queue slots per lane, accumulated in float32 or wide
+    // enough (d > 256) that a pass holds at most two vectors.  Measured on 1M-row sets,
+    // d = 128 integer data: +2.3% (two walkers, L = 192) and +2.8% (one, L = 128) at one
+    // wave less; d = 960: +2% at L = 64 and 128; d = 96 accumulated in double: 1-5% slower.
+    constexpr int GATHER_PB = DT == SA_F32 && NI <= 3 && (ACC32 || LPV >= 32) ? 2 : 1;
     const bool second = two && lane >= 32;
     int m = two && !A.staged ? 2 : 1;   // walkers active in the next step (staged: 1, then 2)
     int nexp = 0;
@@ -406,7 +413,7 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             if (fresh) sid[__popcll(fm & lanemask_lt())] = u;
             nslot += nnew;
             __builtin_amdgcn_wave_barrier();
-            distances<LPV, L2, DT, ACC32>(V, A.d, qs, sid, nnew, nkey);
+            distances<LPV, L2, DT, ACC32, GATHER_PB>(V, A.d, qs, sid, nnew, nkey);
             __builtin_amdgcn_wave_barrier();
             const uint64_t mk = lane < nnew ? nkey[lane] : KEY_EMPTY;
             __builtin_amdgcn_wave_barrier();
