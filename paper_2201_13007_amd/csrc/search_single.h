@@ -223,6 +223,28 @@ __device__ __forceinline__ uint32_t claim(uint32_t *T, int log2cap, uint32_t u, 
     return NO_SLOT;
 }
 
+// The rest of claim() after its first probe, given what that probe's compare-and-swap at
+// block_slot(u, log2cap) returned: lets the caller issue the first probes of a step, go on
+// with other loads, and read the results later.
+__device__ __forceinline__ uint32_t claim_rest(uint32_t *T, int log2cap, uint32_t u, uint32_t old, bool *fresh)
+{
+    const uint32_t mask = (1u << log2cap) - 1u;
+    uint32_t s = block_slot(u, log2cap);
+    *fresh = old == 0u;
+    if (old == 0u || old == u + 1u) return s;
+    const uint32_t step = block_stride(u, log2cap);
+    for (uint32_t probe = 1; probe <= mask; ++probe) {
+        s = (s + step) & mask;
+        old = atomicCAS(&T[s], 0u, u + 1u);
+        if (old == 0u) {
+            *fresh = true;
+            return s;
+        }
+        if (old == u + 1u) return s;
+    }
+    return NO_SLOT;
+}
+
 // Moves the visited set from the table in use (2^t1 entries) into one twice as large,
 // 2^t2 entries at the same address (the region holds the largest; past the table in use
 // it is zero).  The entries are copied out to scratch (the second half of the region) and
@@ -355,6 +377,14 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
     // d = 128 integer data: +2.3% (two walkers, L = 192) and +2.8% (one, L = 128) at one
     // wave less; d = 960: +2% at L = 64 and 128; d = 96 accumulated in double: 1-5% slower.
     constexpr int GATHER_PB = DT == SA_F32 && NI <= 3 && (ACC32 || LPV >= 32) ? 2 : 1;
+    // Gathers alongside the claims (SPEC) where the filter is the full 1024 sets, so that
+    // few vertices that reach the table are already in it (with the 128 sets that d = 960
+    // leaves room for, many are, and each wasted read is a 3.8 KB row: 30-60% slower), and
+    // where the five registers it takes cost no wave that pays (not at NI = 7, 8; at NI = 3
+    // with float32 accumulation the timed two-walker search went 0.5% slower at 5 waves).
+    // Measured on 1M rows: d = 128 one walker +2.5% (L = 128), +2.3% (256), +3.4% (384);
+    // d = 96 in double +4% (one walker, L = 128) and +3% (two, L = 192).
+    constexpr bool SPEC = seen_log2<LPV>() >= 10 && NI != 7 && NI != 8 && !(ACC32 && NI == 3);
     const bool second = two && lane >= 32;
     int m = two && !A.staged ? 2 : 1;   // walkers active in the next step (staged: 1, then 2)
     int nexp = 0;
@@ -406,16 +436,29 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
             const bool known = (cnt > 0u && (sw & tmask) == tag) || (cnt > 1u && ((sw >> tbits) & tmask) == tag) ||
                                (cnt > 2u && ((sw >> (2 * tbits)) & tmask) == tag);
             const bool ask = u >= 0 && !known;
-            if (ask) (void)claim(tbl, t2, (uint32_t)u, &fresh);
+            // The first probe of each claim goes out now.  With SPEC the vectors of every vertex
+            // that passed the filter are read while it is in flight: nearly all of them turn out
+            // new, and the keys of the few found present are dropped after.  Without, the claims
+            // settle first and only new vertices are read.
+            uint32_t old = 0u;
+            if (ask) old = atomicCAS(&tbl[block_slot((uint32_t)u, t2)], 0u, (uint32_t)u + 1u);
             if (ask && filter) seen[hs] = (min(cnt + 1u, ways) << 30) | (((sw << tbits) | tag) & tagbits);
-            const uint64_t fm = __ballot(fresh);
-            const int nnew = __popcll(fm);
-            if (fresh) sid[__popcll(fm & lanemask_lt())] = u;
-            nslot += nnew;
+            if (!SPEC && ask) (void)claim_rest(tbl, t2, (uint32_t)u, old, &fresh);
+            const bool send = SPEC ? ask : fresh;   // the vertices whose vectors are read
+            const uint64_t am = __ballot(send);
+            const int nsend = __popcll(am);
+            const int apos = __popcll(am & lanemask_lt());
+            if (send) sid[apos] = u;
             __builtin_amdgcn_wave_barrier();
-            distances<LPV, L2, DT, ACC32, GATHER_PB>(V, A.d, qs, sid, nnew, nkey);
+            distances<LPV, L2, DT, ACC32, GATHER_PB>(V, A.d, qs, sid, nsend, nkey);
+            if (SPEC && ask) (void)claim_rest(tbl, t2, (uint32_t)u, old, &fresh);
+            nslot += __popcll(__ballot(fresh));
+            if (SPEC) {
+                __builtin_amdgcn_wave_barrier();
+                if (send && !fresh) nkey[apos] = KEY_EMPTY;
+            }
             __builtin_amdgcn_wave_barrier();
-            const uint64_t mk = lane < nnew ? nkey[lane] : KEY_EMPTY;
+            const uint64_t mk = lane < nsend ? nkey[lane] : KEY_EMPTY;
             __builtin_amdgcn_wave_barrier();
             // insert the survivors; the update position is the best place one of them takes
             const uint64_t worst = Q.len == L ? get_key(Q, L - 1) : KEY_EMPTY;
