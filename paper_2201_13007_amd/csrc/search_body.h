@@ -513,7 +513,8 @@ __device__ void migrate_table(const unsigned long long *lh, int llog2, unsigned 
 }
 
 // Job `job` runs query order[job] (or job) in workspace region `region`.
-template <int LPV, int NI, int DT>
+// PB: vectors per lane group in each gather pass (see distances)
+template <int LPV, int NI, int DT, int PB = 1>
 __device__ __forceinline__ void search_body(const KArgs &A, int64_t job, int64_t region)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -653,8 +654,8 @@ __device__ __forceinline__ void search_body(const KArgs &A, int64_t job, int64_t
                     hcount += nclaim;
                     if (fresh) claim[__popcll(cm & lanemask_lt())] = u;
                     __builtin_amdgcn_wave_barrier();
-                    if (l2) distances<LPV, true, DT>(V, A.d, qs, claim, nclaim, nkey);
-                    else distances<LPV, false, DT>(V, A.d, qs, claim, nclaim, nkey);
+                    if (l2) distances<LPV, true, DT, false, PB>(V, A.d, qs, claim, nclaim, nkey);
+                    else distances<LPV, false, DT, false, PB>(V, A.d, qs, claim, nclaim, nkey);
                     __builtin_amdgcn_wave_barrier();
                     const uint64_t mk = lane < nclaim ? nkey[lane] : KEY_EMPTY;
                     __builtin_amdgcn_wave_barrier();
@@ -822,8 +823,8 @@ __device__ __forceinline__ void search_body(const KArgs &A, int64_t job, int64_t
                     const int nclaim = __popcll(cm);
                     if (claimed) claim[__popcll(cm & lanemask_lt())] = u;
                     __builtin_amdgcn_wave_barrier();
-                    if (l2) distances<LPV, true, DT>(V, A.d, qs, claim, nclaim, nkey);
-                    else distances<LPV, false, DT>(V, A.d, qs, claim, nclaim, nkey);
+                    if (l2) distances<LPV, true, DT, false, PB>(V, A.d, qs, claim, nclaim, nkey);
+                    else distances<LPV, false, DT, false, PB>(V, A.d, qs, claim, nclaim, nkey);
                     __builtin_amdgcn_wave_barrier();
                     const uint64_t mk = lane < nclaim ? nkey[lane] : KEY_EMPTY;
                     __builtin_amdgcn_wave_barrier();
