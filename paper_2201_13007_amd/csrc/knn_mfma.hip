@@ -51,6 +51,10 @@ constexpr int MQ = 64;                 // queries per workgroup
 constexpr int MT = 64;                 // base rows per tile
 constexpr int MNT = 256;               // four wavefronts
 constexpr int MBUF = 128;              // candidates buffered per query; flushed when > MBUF - MT
+// the integer kernel's buffer: with its sorted lists k keys long (not rounded up), a
+// workgroup then takes 76 KB of LDS at k = 65 and two fit on a CU (at 128 and a rounded
+// list, 133 KB: one workgroup, one wavefront per SIMD, nothing to hide a barrier or a load)
+constexpr int MBUF_I = 80;
 constexpr int32_t NORM_PAD = 1 << 30;  // norm of padding rows
 
 struct PrepArgs {
@@ -118,13 +122,13 @@ __global__ void __launch_bounds__(MNT) knn_mfma_kernel(MArgs A)
     constexpr int NB = KS <= 4 ? 3 : 2;  // register ring: tiles in flight + the one in use
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     uint64_t *top = reinterpret_cast<uint64_t *>(smem);   // [MQ][kpad] sorted best keys
-    uint64_t *buf = top + (size_t)MQ * A.kpad;             // [MQ][MBUF] unsorted candidates
-    uint64_t *thr = buf + (size_t)MQ * MBUF;               // [MQ] k-th key (or empty)
+    uint64_t *buf = top + (size_t)MQ * A.kpad;             // [MQ][MBUF_I] unsorted candidates
+    uint64_t *thr = buf + (size_t)MQ * MBUF_I;             // [MQ] k-th key (or empty)
     int *cnt = reinterpret_cast<int *>(thr + MQ);          // [MQ] buffered candidates
     int *len = cnt + MQ;                                   // [MQ] length of top
     int *bnd = len + MQ;                                   // [MQ] B_q of the prefilter
     int *qns = bnd + MQ;                                   // [MQ] |q|^2
-    int *need = qns + MQ;  // 1 + index of the last tile in which a buffer passed MBUF - MT
+    int *need = qns + MQ;  // 1 + index of the last tile in which a buffer passed MBUF_I - MT
 
     const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
     const int64_t q0 = (int64_t)blockIdx.x * MQ;
@@ -201,8 +205,8 @@ __global__ void __launch_bounds__(MNT) knn_mfma_kernel(MArgs A)
                             const uint64_t key = make_key((float)(qns[row] + u), (int32_t)col);
                             if (key < thr[row]) {
                                 const int pos = atomicAdd(&cnt[row], 1);
-                                buf[(size_t)row * MBUF + pos] = key;
-                                if (pos + 1 > MBUF - MT) *need = (int)(t + 1);
+                                buf[(size_t)row * MBUF_I + pos] = key;
+                                if (pos + 1 > MBUF_I - MT) *need = (int)(t + 1);
                             }
                         }
                     }
@@ -215,7 +219,7 @@ __global__ void __launch_bounds__(MNT) knn_mfma_kernel(MArgs A)
                 for (int qr = w; qr < MQ; qr += MNT / 64) {
                     const int c = cnt[qr];
                     if (c == 0) continue;
-                    flush_query(top + (size_t)qr * A.kpad, &len[qr], buf + (size_t)qr * MBUF, c, A.k);
+                    flush_query(top + (size_t)qr * A.kpad, &len[qr], buf + (size_t)qr * MBUF_I, c, A.k);
                     __builtin_amdgcn_wave_barrier();
                     if (lane == 0) {
                         cnt[qr] = 0;
@@ -750,9 +754,9 @@ int launch_knn_mfma(const float *base, int64_t n, int32_t d, int64_t ld, const f
     MArgs A;
     A.xb = xb; A.xn = xn; A.qb = qb; A.qn = qn;
     A.n = n; A.nq = nq; A.xrows = xrows;
-    A.dpad = dpad; A.k = k; A.kpad = (k + 63) / 64 * 64; A.exclude_self = exclude_self;
+    A.dpad = dpad; A.k = k; A.kpad = k; A.exclude_self = exclude_self;
     A.ids = ids; A.dists = dists;
-    const size_t lds = 8ull * MQ * A.kpad + 8ull * MQ * MBUF + 8ull * MQ + 4ull * 4 * MQ + 16;
+    const size_t lds = 8ull * MQ * A.kpad + 8ull * MQ * MBUF_I + 8ull * MQ + 4ull * 4 * MQ + 16;
     if (lds > 160u * 1024u) return set_error(SA_EINVAL, "k=%d needs too much LDS", k);
     MKernel kern = pick_kernel(ks, metric);
     if (!kern) return set_error(SA_EUNSUPPORTED, "d=%d", d);

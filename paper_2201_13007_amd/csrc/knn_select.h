@@ -48,7 +48,7 @@ __device__ inline void sort128(unsigned long long &lo, unsigned long long &hi)
     }
 }
 
-// merge the cnt keys of buf (unsorted) into the sorted list top[0..*len), keeping k
+// merge the cnt <= 128 keys of buf (unsorted) into the sorted list top[0..*len), keeping k
 __device__ inline void flush_query(uint64_t *top, int *len, uint64_t *buf, int cnt, int k)
 {
     const int lane = __lane_id();
@@ -56,8 +56,10 @@ __device__ inline void flush_query(uint64_t *top, int *len, uint64_t *buf, int c
     unsigned long long hi = lane + 64 < cnt ? buf[lane + 64] : KEY_EMPTY;
     sort128(lo, hi);
     __builtin_amdgcn_wave_barrier();
-    buf[lane] = lo;
-    buf[lane + 64] = hi;
+    // only the cnt real keys go back (the rest sort to the end as empty): the buffer may be
+    // shorter than 128
+    if (lane < cnt) buf[lane] = lo;
+    if (lane + 64 < cnt) buf[lane + 64] = hi;
     __builtin_amdgcn_wave_barrier();
     const int n = *len;
     // positions of the new keys in the merged order
