@@ -371,12 +371,15 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
     // unchecked entry on lanes 0-31, walker 1 the second on lanes 32-63.
     const bool two = A.M == 2;
     // Two vectors per lane group in each pass of the distance loop (one round trip for 16
-    // new vertices at d = 128 instead of two) where that pays for its sixteen registers:
-    // float32 rows with up to three queue slots per lane, accumulated in float32 or wide
-    // enough (d > 256) that a pass holds at most two vectors.  Measured on 1M-row sets,
-    // d = 128 integer data: +2.3% (two walkers, L = 192) and +2.8% (one, L = 128) at one
-    // wave less; d = 960: +2% at L = 64 and 128; d = 96 accumulated in double: 1-5% slower.
-    constexpr int GATHER_PB = DT == SA_F32 && NI <= 3 && (ACC32 || LPV >= 32) ? 2 : 1;
+    // new vertices at d = 128 instead of two) where that pays for its registers, with up to
+    // three queue slots per lane: float32 rows accumulated in float32 or wide enough
+    // (d > 256) that a pass holds at most two vectors, and bf16 rows up to two slots (at
+    // three the registers would cost two waves of seven).  Measured on 1M-row sets, d = 128
+    // integer data: +2.3% (two walkers, L = 192) and +2.8% (one, L = 128) at one wave less;
+    // d = 960: +2% at L = 64 and 128; d = 96 bf16: +2.8% (two walkers, L = 112, re-ranked);
+    // d = 96 float32 in double 1-5% and fp8 1-4% slower.
+    constexpr int GATHER_PB =
+        (DT == SA_BF16 && NI <= 2) || (DT == SA_F32 && NI <= 3 && (ACC32 || LPV >= 32)) ? 2 : 1;
     // Gathers alongside the claims (SPEC) where the filter is the full 1024 sets, so that
     // few vertices that reach the table are already in it (with the 128 sets that d = 960
     // leaves room for, many are, and each wasted read is a 3.8 KB row: 30-60% slower), and
