@@ -106,6 +106,11 @@ struct SearchLaunch {
 // hold at once, at most njobs: the grid of a persistent launch.  Cached per kernel,
 // LDS size and device.
 hipError_t resident_grid(const void *k, int block, uint32_t lds, int64_t njobs, int64_t *grid);
+// The largest log2 of sets, in [lmin, lmax], for a filter of 4 << l bytes of LDS on top of
+// base that leaves kernel k (block threads) as many workgroups per CU as the smallest
+// does: the occupancy its registers allow is kept, and LDS they leave idle is used.
+// Cached per kernel and device.
+hipError_t lds_fill_log2(const void *k, int block, uint32_t base, int lmin, int lmax, int *out);
 
 // Whether every stored float32 coordinate is an integer such that, for d-dimensional
 // vectors and queries in the same range, every partial sum of a squared distance or

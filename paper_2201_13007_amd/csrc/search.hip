@@ -203,6 +203,40 @@ hipError_t resident_grid(const void *k, int block, uint32_t lds, int64_t njobs, 
     return hipSuccess;
 }
 
+hipError_t lds_fill_log2(const void *k, int block, uint32_t base, int lmin, int lmax, int *out)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, int> cache;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find({k, dev});
+        if (it != cache.end()) {
+            *out = it->second;
+            return hipSuccess;
+        }
+    }
+    int want = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&want, k, block, base + (4u << lmin));
+    if (e != hipSuccess) return e;
+    int l = lmin;
+    for (int c = lmax; c > lmin; --c) {
+        int got = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&got, k, block, base + (4u << c));
+        if (e != hipSuccess) return e;
+        if (got >= want) {
+            l = c;
+            break;
+        }
+    }
+    std::lock_guard<std::mutex> g(mu);
+    cache[{k, dev}] = l;
+    *out = l;
+    return hipSuccess;
+}
+
 int launch_search(const SearchLaunch &a, hipStream_t stream)
 {
     int llog2, glog2, max_sub;

@@ -86,6 +86,7 @@ struct KArgs {
     // accumulates in float32, pass 0 takes the others; -1: one pass takes every query
     int32_t int_lo, int_hi, acc_pass;
     int32_t idbits;              // vertex ids fit in idbits bits (2^idbits >= n)
+    int32_t seen_log2;           // single-worker kernel: log2 of the seen filter's sets (set by its launcher)
     uint32_t o_skey, o_srank, o_schk, o_pub, o_newkey, o_claim, o_ctrl, o_hash, o_q;
     // batches: per-query L and k (null: L and k above) and the query each workgroup
     // runs (null: workgroup b runs query b)

@@ -36,21 +36,25 @@ namespace single_detail {
 using search_detail::KArgs;
 using search_detail::NO_SLOT;
 
+// LDS of a wavefront besides the filter of recently seen vertices: new keys, new ids, the
+// query row
+template <int LPV>
+constexpr uint32_t single_lds_base()
+{
+    return 64 * 8 + 64 * 4 + 64 * LPV;
+}
+
 // log2 of the sets of the per-query LDS filter of recently seen vertices (one 32-bit word
-// per set): the largest (up to 1024 sets, 4 KB) that keeps a wavefront's LDS within
-// 160 KB / 28, so that LDS never holds a CU below the 28 wavefronts the registers allow
+// per set) that fits whatever the kernel's occupancy: the largest (up to 1024 sets, 4 KB)
+// that keeps a wavefront's LDS within 160 KB / 28.  The launcher grows the filter beyond it
+// (up to 2048 sets) where the kernel's registers hold fewer wavefronts per CU than that
+// (lds_fill_log2), so that the LDS they leave idle serves the filter.
 template <int LPV>
 constexpr int seen_log2()
 {
     int l = 10;
-    while (l > 6 && 64 * 8 + 64 * 4 + 64 * LPV + (4 << l) > 160 * 1024 / 28) --l;
+    while (l > 6 && single_lds_base<LPV>() + (4u << l) > 160u * 1024u / 28u) --l;
     return l;
-}
-
-template <int LPV>
-constexpr uint32_t single_lds_bytes()
-{
-    return 64 * 8 + 64 * 4 + 64 * LPV + (4u << seen_log2<LPV>());
 }
 using search_detail::VecSrc;
 using search_detail::bpermute64;
@@ -297,8 +301,8 @@ __device__ __forceinline__ void single_query(const KArgs &A, int64_t qi, uint32_
     // tags in its top two bits and up to W = min(3, 30 / tb) tags below, newest lowest; a new
     // tag pushes the oldest out.  (Ids of more than 15 + SEEN_LOG2 bits: no filter.)
     uint32_t *const seen = reinterpret_cast<uint32_t *>(qs + 16 * LPV);
-    constexpr int SEEN_LOG2 = seen_log2<LPV>();
-    constexpr int SEEN = 1 << SEEN_LOG2;
+    const int SEEN_LOG2 = A.seen_log2;
+    const int SEEN = 1 << SEEN_LOG2;
     const int hbits = A.idbits > SEEN_LOG2 ? A.idbits : SEEN_LOG2 + 1;
     const int tbits = hbits - SEEN_LOG2;
     const bool filter = tbits <= 15;
@@ -561,18 +565,24 @@ __global__ void __launch_bounds__(64) search_single_loop(KArgs A)
 template <int LPV, int NI, int DT, bool ACC32>
 hipError_t launch1(const KArgs &A, int64_t nq, hipStream_t s)
 {
-    const uint32_t lds = single_lds_bytes<LPV>();
+    constexpr uint32_t base = single_lds_base<LPV>();
+    KArgs B = A;
     if (A.jobctr) {
         auto k = A.metric == SA_L2 ? search_single_loop<LPV, NI, true, DT, ACC32>
                                    : search_single_loop<LPV, NI, false, DT, ACC32>;
-        int64_t grid = nq;
-        const hipError_t e = resident_grid(reinterpret_cast<const void *>(k), 64, lds, nq, &grid);
+        hipError_t e = lds_fill_log2(reinterpret_cast<const void *>(k), 64, base, seen_log2<LPV>(), 11, &B.seen_log2);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64), lds, s, A);
+        const uint32_t lds = base + (4u << B.seen_log2);
+        int64_t grid = nq;
+        e = resident_grid(reinterpret_cast<const void *>(k), 64, lds, nq, &grid);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(64), lds, s, B);
         return hipGetLastError();
     }
     auto k = A.metric == SA_L2 ? search_single<LPV, NI, true, DT, ACC32> : search_single<LPV, NI, false, DT, ACC32>;
-    hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64), lds, s, A);
+    const hipError_t e = lds_fill_log2(reinterpret_cast<const void *>(k), 64, base, seen_log2<LPV>(), 11, &B.seen_log2);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(64), base + (4u << B.seen_log2), s, B);
     return hipGetLastError();
 }
 
